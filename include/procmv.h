@@ -1,0 +1,166 @@
+/*
+ * procmv: block-procedural matrix-free Hamiltonian product on MI355X (gfx950).
+ *
+ * C ABI of libprocmv.so.  The library applies a dense Hermitian operator H of
+ * dimension D to one or more vectors without ever holding the D x D matrix:
+ * blocks H^[n,m] are generated on the fly from a seed or a closed form, or
+ * read from a partial or full cache of canonical block pairs in device memory,
+ * and applied inside the same kernel (paper: Sec. II, Eqs. blockham,
+ * blockmatvec, blockmatvecindex; Sec. III, Eqs. single_block_apply,
+ * output_block_apply, and the block sources "seeded generation", "analytic
+ * generation", "fused action", "full caching", "partial caching").
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Vectors are complex64 (interleaved float re, im), vector-contiguous:
+ *    vector v of a block of nvec vectors starts at base + v * ld complex
+ *    elements, ld >= D.  In PyTorch terms: a (nvec, D) complex64 tensor.
+ *  - Pointers named X, Y, psi, out_dev are DEVICE pointers owned by the caller
+ *    (allocate them with PyTorch or hipMalloc).  The library never frees them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is enqueued on it and calls return without synchronising,
+ *    except where a call says it synchronises.
+ *  - Every call returns a procmv_status.  Argument errors are detected on the
+ *    host before anything is enqueued; launch errors are reported by the call
+ *    that launched; faults inside kernels surface at the next synchronisation.
+ *    procmv_last_error() gives a message for the calling thread.
+ *  - Results are deterministic: the same inputs give bit-identical outputs on
+ *    every run (fixed-order reductions, no floating-point atomics).
+ *  - An operator handle is not thread-safe: serialise calls on one handle.
+ */
+#ifndef PROCMV_H
+#define PROCMV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct procmv_op* procmv_op_t;
+
+typedef enum {
+    PROCMV_OK = 0,
+    PROCMV_ERR_INVALID_ARG = 1,
+    PROCMV_ERR_OOM = 2,
+    PROCMV_ERR_INFEASIBLE_PLAN = 3,
+    PROCMV_ERR_NOT_PLANNED = 4,
+    PROCMV_ERR_HIP = 5,
+    PROCMV_ERR_INTERNAL = 6
+} procmv_status;
+
+/* Block sources (paper Sec. III): seeded Philox-GUE and analytic sinc-DVR. */
+typedef enum {
+    PROCMV_GEN_PHILOX_GUE = 0,
+    PROCMV_GEN_SINC_DVR = 1
+} procmv_generator;
+
+/* Storage modes (paper Sec. III, "full caching", "partial caching"). */
+typedef enum {
+    PROCMV_PROCEDURAL = 0,
+    PROCMV_PARTIAL = 1,
+    PROCMV_FULL = 2
+} procmv_strategy;
+
+/* Arithmetic of the block products. */
+typedef enum {
+    PROCMV_FP32 = 0,       /* binary32 entries, binary32 accumulation        */
+    PROCMV_SPLIT_BF16 = 1  /* hi/lo bfloat16 split on MFMA, fp32 accumulation */
+} procmv_precision;
+
+/* Sinc-DVR parameters (analytic generation, paper Sec. III).  Grid
+ * x_i = x_min + i dx, dx = (x_max - x_min)/(D - 1); entries
+ * T_ij = (-1)^(i-j) / (mass dx^2 (i-j)^2) for i != j and
+ * H_ii = pi^2/(6 mass dx^2) + mass omega^2 x_i^2 / 2.  With compensate != 0
+ * the constant diagonal also absorbs the binary32 rounding error of the
+ * off-diagonal kinetic entries (keeps the exact zero row sum of the kinetic
+ * stencil).  Pass NULL for the defaults x in [-20, 20], mass = omega = 1,
+ * compensate = 1. */
+typedef struct {
+    double x_min, x_max, mass, omega;
+    int32_t compensate;
+} procmv_dvr_params;
+
+/* Create an operator.  Philox-GUE (paper Sec. III, seeded generation; keyed
+ * on global (i, j) so the matrix does not depend on the partition, Sec. II):
+ * H_ij for i < j has re, im ~ N(0, 1/(2D)), H_ji = conj(H_ij), H_ii ~
+ * N(0, 1/D) real, drawn from Philox4x32-10 with key (seed & 0xffffffff,
+ * seed >> 32) and counter (i, j, 0, 0).  gen_params: NULL for GUE,
+ * procmv_dvr_params* (or NULL) for DVR.  D in [1, 2^31).  No device memory is
+ * touched until procmv_plan.  *out receives the handle. */
+procmv_status procmv_create_operator(procmv_generator gen, uint64_t seed,
+                                     int64_t D, const void* gen_params,
+                                     procmv_op_t* out);
+
+/* Choose the execution plan (paper Sec. IV: block size, storage mode, cache
+ * budget / number of cached canonical pairs, Eq. partial_cache_pairs).
+ * block_size b: multiple of 64, 64 <= b; the last block is ragged when
+ * D % b != 0.  strategy PROCMV_PARTIAL caches P = floor(cache_fraction *
+ * N_pair) canonical pairs (n <= m) of the N_pair = N_blk (N_blk + 1) / 2,
+ * spread over block rows; PROCMV_FULL caches all; PROCMV_PROCEDURAL none.
+ * Allocates the cache and fills it on `stream`, then SYNCHRONISES the stream.
+ * Returns PROCMV_ERR_OOM if the cache cannot be allocated.  Re-planning
+ * releases the previous plan's memory. */
+procmv_status procmv_plan(procmv_op_t H, int32_t block_size,
+                          procmv_strategy strategy, double cache_fraction,
+                          procmv_precision precision, void* stream);
+
+/* Y = H X for nvec vectors (paper Eq. generic_multivector, Y = A X).  X and Y
+ * are device complex64 (nvec, ld*) buffers that must not overlap.  Needs a
+ * plan.  Enqueues on `stream`; does not synchronise. */
+procmv_status procmv_apply(procmv_op_t H, const void* X, int64_t ldx,
+                           void* Y, int64_t ldy, int32_t nvec, void* stream);
+
+/* Default spectral bounds used by procmv_chebyshev_propagate when spec_R is
+ * not positive: GUE c = 0, R = 2.5 (semicircle edge 2 plus margin); DVR
+ * E_min = 0, E_max = pi^2/(2 mass dx^2) + max V. */
+procmv_status procmv_spectral_bounds(procmv_op_t H, double* c, double* R);
+
+/* Chebyshev order for argument x = R dt and coefficient tolerance tol: the
+ * first k >= x with 2|J_k(x)| < tol and 2|J_{k+1}(x)| < tol. */
+int32_t procmv_cheb_order(double x, double tol);
+
+/* Real-time propagation psi <- exp(-i H dt)^nsteps psi by the centered
+ * Chebyshev expansion (paper Sec. VII: Ht = (H - c)/R, q_0 = psi,
+ * q_1 = Ht q_0, q_{l+1} = 2 Ht q_l - q_{l-1}; coefficients
+ * (2 - delta_k0)(-i)^k J_k(R dt), Tal-Ezer & Kosloff).  Each step runs K + 1
+ * terms (K <= 0: procmv_cheb_order(R dt, 1e-10)); the coefficient sum is
+ * accumulated in binary64 and rounded to complex64 once per step.  psi:
+ * device complex64 (nvec, ld), updated in place.  spec_R <= 0 selects
+ * procmv_spectral_bounds.  norms_out (HOST, may be NULL): nsteps * nvec
+ * binary64 norms ||psi|| after each step.  SYNCHRONISES the stream when
+ * norms_out is given. */
+procmv_status procmv_chebyshev_propagate(procmv_op_t H, void* psi, int64_t ld,
+                                         int32_t nvec, double dt, int32_t K,
+                                         int32_t nsteps, double spec_c,
+                                         double spec_R, double* norms_out,
+                                         void* stream);
+
+/* Test hook: the generated binary32 entries H[r0:r0+nr, c0:c0+nc] written to
+ * out_dev (device, complex64, row-major nr x nc), through the same generator
+ * code as the products.  Needs no plan. */
+procmv_status procmv_get_entries(procmv_op_t H, int64_t r0, int64_t c0,
+                                 int32_t nr, int32_t nc, void* out_dev,
+                                 void* stream);
+
+/* Plan summary (host): block size, block count, canonical pairs, cached
+ * pairs, cache bytes, workspace bytes. */
+typedef struct {
+    int64_t D;
+    int32_t block_size, n_blk;
+    int64_t n_pair, p_cache;
+    int64_t cache_bytes, work_bytes;
+    int32_t strategy, precision;
+} procmv_plan_info_t;
+procmv_status procmv_plan_info(procmv_op_t H, procmv_plan_info_t* info);
+
+/* Release the operator and every device buffer it owns. NULL is ignored. */
+void procmv_destroy(procmv_op_t H);
+
+/* Message of the calling thread's last error ("" if none). */
+const char* procmv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PROCMV_H */

@@ -1,0 +1,579 @@
+// C ABI of libprocmv.so: operators, plans, products and propagation.
+// The paper passages each call implements are cited in include/procmv.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/procmv.h"
+#include "kernels.h"
+
+using namespace procmv;
+
+namespace {
+
+thread_local std::string g_err;
+
+procmv_status fail(procmv_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                        \
+    do {                                                                     \
+        hipError_t e_ = (expr);                                              \
+        if (e_ != hipSuccess)                                                \
+            return fail(e_ == hipErrorOutOfMemory ? PROCMV_ERR_OOM           \
+                                                  : PROCMV_ERR_HIP,          \
+                        "%s: %s", #expr, hipGetErrorString(e_));             \
+    } while (0)
+
+template <class T>
+void dfree(T*& p)
+{
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+}  // namespace
+
+struct procmv_op {
+    int gen = 0;
+    uint64_t seed = 0;
+    int64_t D = 0;
+    procmv_dvr_params dvr{};
+    // Philox-GUE scales (binary32, rounded once from binary64)
+    float s_off = 0.f, s_diag = 0.f;
+    // sinc-DVR: device tables and binary64 constants
+    float* d_tk = nullptr;
+    float* d_v = nullptr;
+    double d_const = 0.0;   // constant diagonal paired with the binary32 tables
+    double dx = 0.0, vmax = 0.0;
+    // plan
+    bool planned = false;
+    int32_t b = 0, n_blk = 0;
+    int strategy = 0, precision = 0;
+    double frac = 0.0;
+    int64_t n_pair = 0, p_cache = 0;
+    int32_t* d_pair_slot = nullptr;
+    void* d_slots = nullptr;
+    int2* d_pairs = nullptr;
+    int32_t n_super = 0;
+    int64_t n_st = 0;
+    int2* d_st = nullptr;
+    // workspace
+    float2* d_P = nullptr;
+    size_t P_bytes = 0;
+    float2* d_q = nullptr;
+    size_t q_bytes = 0;
+    double2* d_acc = nullptr;
+    size_t acc_bytes = 0;
+    double* d_norm = nullptr;
+    size_t norm_bytes = 0;
+
+    size_t slot_elem() const { return gen == 0 ? sizeof(float2) : sizeof(float); }
+
+    SourceArgs source() const
+    {
+        SourceArgs s{};
+        s.gen = gen;
+        s.gue.k0 = (uint32_t)seed;
+        s.gue.k1 = (uint32_t)(seed >> 32);
+        s.gue.s_off = s_off;
+        s.gue.s_diag = s_diag;
+        s.dvr.tk = d_tk;
+        s.dvr.v = d_v;
+        s.pair_slot = (planned && p_cache > 0) ? d_pair_slot : nullptr;
+        s.slots = d_slots;
+        s.b = b;
+        s.n_blk = n_blk;
+        return s;
+    }
+
+    void release_plan()
+    {
+        dfree(d_pair_slot);
+        dfree(d_slots);
+        dfree(d_pairs);
+        dfree(d_st);
+        planned = false;
+        p_cache = 0;
+    }
+
+    ~procmv_op()
+    {
+        release_plan();
+        dfree(d_tk);
+        dfree(d_v);
+        dfree(d_P);
+        dfree(d_q);
+        dfree(d_acc);
+        dfree(d_norm);
+    }
+};
+
+namespace {
+
+// Grow a device buffer to at least `bytes`.
+template <class T>
+procmv_status ensure(T*& p, size_t& have, size_t bytes)
+{
+    if (have >= bytes) return PROCMV_OK;
+    dfree(p);
+    have = 0;
+    HIP_TRY(hipMalloc((void**)&p, bytes));
+    have = bytes;
+    return PROCMV_OK;
+}
+
+// hi + lo binary32 pair of a binary64 value.
+void split_f32(double v, float& hi, float& lo)
+{
+    hi = (float)v;
+    lo = (float)(v - (double)hi);
+}
+
+// Largest binary32 value not above x (x > 0).
+float f32_down(double x)
+{
+    float f = (float)x;
+    if ((double)f > x) f = std::nextafter(f, 0.0f);
+    return f;
+}
+
+// J_0(x) .. J_kmax(x), x >= 0, Miller's backward recurrence normalised by
+// J_0 + 2 sum J_2k = 1.
+std::vector<double> bessel_j(double x, int kmax)
+{
+    std::vector<double> out(kmax + 1, 0.0);
+    if (x == 0.0) {
+        out[0] = 1.0;
+        return out;
+    }
+    const int top = (int)std::max((double)kmax, x) + 30 +
+                    (int)(20.0 * std::cbrt(std::max(x, 1.0)));
+    std::vector<double> j(top + 2, 0.0);
+    j[top] = 1e-300;
+    for (int k = top; k > 0; --k) {
+        j[k - 1] = (2.0 * k / x) * j[k] - j[k + 1];
+        if (std::fabs(j[k - 1]) > 1e250)
+            for (int q = k - 1; q <= top; ++q) j[q] *= 1e-250;
+    }
+    double norm = j[0];
+    for (int k = 2; k <= top; k += 2) norm += 2.0 * j[k];
+    for (int k = 0; k <= kmax; ++k) out[k] = j[k] / norm;
+    return out;
+}
+
+procmv_status check_op(procmv_op_t H)
+{
+    if (!H) return fail(PROCMV_ERR_INVALID_ARG, "null operator handle");
+    return PROCMV_OK;
+}
+
+procmv_status upload_dvr(procmv_op* op)
+{
+    const int64_t D = op->D;
+    const double dx = (op->dvr.x_max - op->dvr.x_min) / (double)(D - 1);
+    const double inv_mdx2 = 1.0 / (op->dvr.mass * dx * dx);
+    const double kpot = 0.5 * op->dvr.mass * op->dvr.omega * op->dvr.omega;
+    std::vector<float> tk(D, 0.f), v(D, 0.f);
+    double err = 0.0, vmax = 0.0;
+    for (int64_t k = 1; k < D; ++k) {
+        const double t = ((k & 1) ? -inv_mdx2 : inv_mdx2) / ((double)k * (double)k);
+        tk[k] = (float)t;
+        err += (double)tk[k] - t;
+    }
+    for (int64_t i = 0; i < D; ++i) {
+        const double x = op->dvr.x_min + (double)i * dx;
+        const double vv = kpot * (x * x);
+        v[i] = (float)vv;
+        vmax = std::max(vmax, vv);
+    }
+    const double d0 = (M_PI * M_PI / 6.0) * inv_mdx2;
+    op->d_const = op->dvr.compensate ? d0 - 2.0 * err : d0;
+    op->dx = dx;
+    op->vmax = vmax;
+    HIP_TRY(hipMalloc((void**)&op->d_tk, D * sizeof(float)));
+    HIP_TRY(hipMalloc((void**)&op->d_v, D * sizeof(float)));
+    HIP_TRY(hipMemcpy(op->d_tk, tk.data(), D * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(op->d_v, v.data(), D * sizeof(float), hipMemcpyHostToDevice));
+    return PROCMV_OK;
+}
+
+// Tile product of nv (1, 2, 4 or 8) vectors into the partial buffer.
+procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
+                        hipStream_t s)
+{
+    const size_t ldp = (size_t)op->D;
+    const size_t need = (size_t)(op->n_super + 1) * nv * ldp * sizeof(float2);
+    procmv_status st = ensure(op->d_P, op->P_bytes, need);
+    if (st != PROCMV_OK) return st;
+    TileArgs a{};
+    a.src = op->source();
+    a.D = (int32_t)op->D;
+    a.n_super = op->n_super;
+    a.st_list = op->d_st;
+    a.X = X;
+    a.ldx = ldx;
+    a.P = op->d_P;
+    a.ldp = (int64_t)ldp;
+    HIP_TRY(launch_tile_apply(a, nv, (int)op->n_st, s));
+    return PROCMV_OK;
+}
+
+ReduceArgs reduce_args(procmv_op* op, int nv)
+{
+    ReduceArgs r{};
+    r.D = (int32_t)op->D;
+    r.nv = nv;
+    r.n_slots = op->n_super + 1;
+    r.P = op->d_P;
+    r.ldp = op->D;
+    r.alpha = 1.0f;
+    return r;
+}
+
+int chunk_nv(int remaining)
+{
+    return remaining >= 8 ? 8 : remaining >= 4 ? 4 : remaining >= 2 ? 2 : 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* procmv_last_error(void) { return g_err.c_str(); }
+
+procmv_status procmv_create_operator(procmv_generator gen, uint64_t seed,
+                                     int64_t D, const void* gen_params,
+                                     procmv_op_t* out)
+{
+    if (!out) return fail(PROCMV_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    if (gen != PROCMV_GEN_PHILOX_GUE && gen != PROCMV_GEN_SINC_DVR)
+        return fail(PROCMV_ERR_INVALID_ARG, "unknown generator %d", (int)gen);
+    if (D < 1 || D >= (int64_t(1) << 31))
+        return fail(PROCMV_ERR_INVALID_ARG, "D = %lld outside [1, 2^31)", (long long)D);
+    if (gen == PROCMV_GEN_SINC_DVR && D < 2)
+        return fail(PROCMV_ERR_INVALID_ARG, "sinc-DVR needs D >= 2");
+    procmv_op* op = new procmv_op();
+    op->gen = (int)gen;
+    op->seed = seed;
+    op->D = D;
+    if (gen == PROCMV_GEN_PHILOX_GUE) {
+        op->s_off = (float)std::sqrt(1.0 / (2.0 * (double)D));
+        op->s_diag = (float)std::sqrt(1.0 / (double)D);
+    } else {
+        if (gen_params) op->dvr = *(const procmv_dvr_params*)gen_params;
+        else op->dvr = procmv_dvr_params{-20.0, 20.0, 1.0, 1.0, 1};
+        if (!(op->dvr.x_max > op->dvr.x_min) || !(op->dvr.mass > 0)) {
+            delete op;
+            return fail(PROCMV_ERR_INVALID_ARG, "bad DVR parameters");
+        }
+        procmv_status st = upload_dvr(op);
+        if (st != PROCMV_OK) {
+            delete op;
+            return st;
+        }
+    }
+    *out = op;
+    return PROCMV_OK;
+}
+
+void procmv_destroy(procmv_op_t H) { delete H; }
+
+procmv_status procmv_plan(procmv_op_t H, int32_t block_size,
+                          procmv_strategy strategy, double cache_fraction,
+                          procmv_precision precision, void* stream)
+{
+    procmv_status st = check_op(H);
+    if (st != PROCMV_OK) return st;
+    if (block_size < 64 || block_size % 64 != 0)
+        return fail(PROCMV_ERR_INVALID_ARG, "block size %d: need a multiple of 64", block_size);
+    if (strategy < PROCMV_PROCEDURAL || strategy > PROCMV_FULL)
+        return fail(PROCMV_ERR_INVALID_ARG, "unknown strategy %d", (int)strategy);
+    if (strategy == PROCMV_PARTIAL && !(cache_fraction >= 0.0 && cache_fraction <= 1.0))
+        return fail(PROCMV_ERR_INVALID_ARG, "cache fraction %g outside [0, 1]", cache_fraction);
+    if (precision != PROCMV_FP32 && precision != PROCMV_SPLIT_BF16)
+        return fail(PROCMV_ERR_INVALID_ARG, "unknown precision %d", (int)precision);
+    if (precision == PROCMV_SPLIT_BF16)
+        return fail(PROCMV_ERR_INVALID_ARG, "split-bf16 precision is not available in this build");
+    hipStream_t s = (hipStream_t)stream;
+    H->release_plan();
+    const int64_t D = H->D;
+    H->b = block_size;
+    H->n_blk = (int32_t)((D + block_size - 1) / block_size);
+    H->strategy = (int)strategy;
+    H->precision = (int)precision;
+    H->frac = strategy == PROCMV_FULL ? 1.0 : strategy == PROCMV_PARTIAL ? cache_fraction : 0.0;
+    const int64_t nb = H->n_blk;
+    H->n_pair = nb * (nb + 1) / 2;
+    // canonical pairs in row-major order; pair q is cached when
+    // floor((q + 1) f) > floor(q f), which spreads the cached fraction evenly
+    std::vector<int32_t> slot(nb * nb, -1);
+    std::vector<int2> pairs;
+    int64_t q = 0;
+    for (int64_t n = 0; n < nb; ++n)
+        for (int64_t m = n; m < nb; ++m, ++q) {
+            bool take = false;
+            if (strategy == PROCMV_FULL) take = true;
+            else if (strategy == PROCMV_PARTIAL)
+                take = std::floor((double)(q + 1) * H->frac) > std::floor((double)q * H->frac);
+            if (take) {
+                slot[n * nb + m] = (int32_t)pairs.size();
+                pairs.push_back(make_int2((int)n, (int)m));
+            }
+        }
+    H->p_cache = (int64_t)pairs.size();
+    // super-tile list
+    H->n_super = (int32_t)((D + kSuper - 1) / kSuper);
+    std::vector<int2> sts;
+    sts.reserve((size_t)H->n_super * (H->n_super + 1) / 2);
+    for (int r = 0; r < H->n_super; ++r)
+        for (int c = r; c < H->n_super; ++c) sts.push_back(make_int2(r, c));
+    H->n_st = (int64_t)sts.size();
+    HIP_TRY(hipMalloc((void**)&H->d_st, sts.size() * sizeof(int2)));
+    HIP_TRY(hipMemcpy(H->d_st, sts.data(), sts.size() * sizeof(int2), hipMemcpyHostToDevice));
+    if (H->p_cache > 0) {
+        const size_t bytes = (size_t)H->p_cache * block_size * block_size * H->slot_elem();
+        hipError_t e = hipMalloc(&H->d_slots, bytes);
+        if (e != hipSuccess) {
+            H->d_slots = nullptr;
+            H->release_plan();
+            (void)hipGetLastError();
+            return fail(PROCMV_ERR_OOM, "cache of %lld pairs (%zu bytes) does not fit: %s",
+                        (long long)H->p_cache, bytes, hipGetErrorString(e));
+        }
+        HIP_TRY(hipMalloc((void**)&H->d_pair_slot, slot.size() * sizeof(int32_t)));
+        HIP_TRY(hipMemcpy(H->d_pair_slot, slot.data(), slot.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+        HIP_TRY(hipMalloc((void**)&H->d_pairs, pairs.size() * sizeof(int2)));
+        HIP_TRY(hipMemcpy(H->d_pairs, pairs.data(), pairs.size() * sizeof(int2),
+                          hipMemcpyHostToDevice));
+        SourceArgs src = H->source();
+        HIP_TRY(launch_cache_fill(src, (int32_t)D, H->d_pairs, H->p_cache, H->d_slots, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    H->planned = true;
+    return PROCMV_OK;
+}
+
+procmv_status procmv_plan_info(procmv_op_t H, procmv_plan_info_t* info)
+{
+    procmv_status st = check_op(H);
+    if (st != PROCMV_OK) return st;
+    if (!info) return fail(PROCMV_ERR_INVALID_ARG, "info is null");
+    if (!H->planned) return fail(PROCMV_ERR_NOT_PLANNED, "operator has no plan");
+    info->D = H->D;
+    info->block_size = H->b;
+    info->n_blk = H->n_blk;
+    info->n_pair = H->n_pair;
+    info->p_cache = H->p_cache;
+    info->cache_bytes = H->p_cache * (int64_t)H->b * H->b * (int64_t)H->slot_elem();
+    info->work_bytes = (int64_t)(H->n_super + 1) * 8 * H->D * (int64_t)sizeof(float2);
+    info->strategy = H->strategy;
+    info->precision = H->precision;
+    return PROCMV_OK;
+}
+
+procmv_status procmv_apply(procmv_op_t H, const void* X, int64_t ldx, void* Y,
+                           int64_t ldy, int32_t nvec, void* stream)
+{
+    procmv_status st = check_op(H);
+    if (st != PROCMV_OK) return st;
+    if (!H->planned) return fail(PROCMV_ERR_NOT_PLANNED, "procmv_apply before procmv_plan");
+    if (!X || !Y) return fail(PROCMV_ERR_INVALID_ARG, "null vector pointer");
+    if (nvec < 1) return fail(PROCMV_ERR_INVALID_ARG, "nvec = %d", nvec);
+    if (ldx < H->D || ldy < H->D)
+        return fail(PROCMV_ERR_INVALID_ARG, "leading dimensions must be >= D");
+    const char* xb = (const char*)X;
+    const char* yb = (const char*)Y;
+    const size_t xs = ((size_t)(nvec - 1) * ldx + H->D) * sizeof(float2);
+    const size_t ys = ((size_t)(nvec - 1) * ldy + H->D) * sizeof(float2);
+    if (xb < yb + ys && yb < xb + xs)
+        return fail(PROCMV_ERR_INVALID_ARG, "X and Y overlap");
+    hipStream_t s = (hipStream_t)stream;
+    float bhi = 0.f, blo = 0.f;
+    if (H->gen == 1) split_f32(H->d_const, bhi, blo);
+    for (int v0 = 0; v0 < nvec;) {
+        const int nv = chunk_nv(nvec - v0);
+        const float2* Xc = (const float2*)X + (size_t)v0 * ldx;
+        float2* Yc = (float2*)Y + (size_t)v0 * ldy;
+        st = run_tiles(H, Xc, ldx, nv, s);
+        if (st != PROCMV_OK) return st;
+        ReduceArgs r = reduce_args(H, nv);
+        r.X = Xc;
+        r.ldx = ldx;
+        r.Y = Yc;
+        r.ldy = ldy;
+        r.beta_hi = bhi;
+        r.beta_lo = blo;
+        HIP_TRY(launch_reduce(r, Epi::kApply, s));
+        v0 += nv;
+    }
+    return PROCMV_OK;
+}
+
+procmv_status procmv_spectral_bounds(procmv_op_t H, double* c, double* R)
+{
+    procmv_status st = check_op(H);
+    if (st != PROCMV_OK) return st;
+    if (!c || !R) return fail(PROCMV_ERR_INVALID_ARG, "null output");
+    if (H->gen == 0) {
+        *c = 0.0;
+        *R = 2.5;
+    } else {
+        const double e_min = 0.0;
+        const double e_max = M_PI * M_PI / (2.0 * H->dvr.mass * H->dx * H->dx) + H->vmax;
+        *c = 0.5 * (e_max + e_min);
+        *R = 0.5 * (e_max - e_min);
+    }
+    return PROCMV_OK;
+}
+
+int32_t procmv_cheb_order(double x, double tol)
+{
+    if (!(x >= 0.0) || !(tol > 0.0)) return -1;
+    const int kmax = (int)x + 60 + (int)(30.0 * std::cbrt(std::max(x, 1.0)));
+    std::vector<double> j = bessel_j(x, kmax + 1);
+    for (int k = (int)std::ceil(x); k + 1 <= kmax + 1; ++k)
+        if (2.0 * std::fabs(j[k]) < tol && 2.0 * std::fabs(j[k + 1]) < tol) return k;
+    return -1;
+}
+
+procmv_status procmv_chebyshev_propagate(procmv_op_t H, void* psi, int64_t ld,
+                                         int32_t nvec, double dt, int32_t K,
+                                         int32_t nsteps, double spec_c,
+                                         double spec_R, double* norms_out,
+                                         void* stream)
+{
+    procmv_status st = check_op(H);
+    if (st != PROCMV_OK) return st;
+    if (!H->planned) return fail(PROCMV_ERR_NOT_PLANNED, "propagation before procmv_plan");
+    if (!psi) return fail(PROCMV_ERR_INVALID_ARG, "psi is null");
+    if (nvec < 1 || nsteps < 0 || ld < H->D || !(dt >= 0.0))
+        return fail(PROCMV_ERR_INVALID_ARG, "bad nvec/nsteps/ld/dt");
+    double c = spec_c, R = spec_R;
+    if (!(R > 0.0)) {
+        st = procmv_spectral_bounds(H, &c, &R);
+        if (st != PROCMV_OK) return st;
+    }
+    // 1/R exact in binary32: the half-width is widened to 1/alpha.
+    const float alpha = f32_down(1.0 / R);
+    const double Reff = 1.0 / (double)alpha;
+    if (K <= 0) K = procmv_cheb_order(Reff * dt, 1e-10);
+    if (K < 1) return fail(PROCMV_ERR_INVALID_ARG, "Chebyshev order could not be set");
+    const std::vector<double> j = bessel_j(Reff * dt, K);
+    std::vector<double2> a(K + 1);
+    for (int k = 0; k <= K; ++k) {
+        const double m = (k == 0 ? 1.0 : 2.0) * j[k];
+        // (-i)^k
+        const int q = k & 3;
+        a[k] = q == 0 ? double2{m, 0.0} : q == 1 ? double2{0.0, -m}
+             : q == 2 ? double2{-m, 0.0} : double2{0.0, m};
+    }
+    const double2 phase{std::cos(c * dt), -std::sin(c * dt)};
+    const double dconst = H->gen == 1 ? H->d_const : 0.0;
+    float bhi, blo;
+    split_f32((double)alpha * (dconst - c), bhi, blo);
+    hipStream_t s = (hipStream_t)stream;
+
+    for (int v0 = 0; v0 < nvec;) {
+        const int nv = chunk_nv(nvec - v0);
+        float2* P0 = (float2*)psi + (size_t)v0 * ld;
+        const size_t D = (size_t)H->D;
+        st = ensure(H->d_q, H->q_bytes, (size_t)nv * D * sizeof(float2));
+        if (st != PROCMV_OK) return st;
+        st = ensure(H->d_acc, H->acc_bytes, (size_t)nv * D * sizeof(double2));
+        if (st != PROCMV_OK) return st;
+        st = ensure(H->d_norm, H->norm_bytes, (size_t)nv * sizeof(double));
+        if (st != PROCMV_OK) return st;
+        for (int step = 0; step < nsteps; ++step) {
+            // q0 lives in psi (ld), q1 in d_q (ld = D); the recurrence
+            // overwrites the older of the two.
+            float2* qa = P0;
+            int64_t lda = ld;
+            float2* qb = H->d_q;
+            int64_t ldb = (int64_t)D;
+            st = run_tiles(H, qa, lda, nv, s);
+            if (st != PROCMV_OK) return st;
+            ReduceArgs r = reduce_args(H, nv);
+            r.X = qa;
+            r.ldx = lda;
+            r.Yq1 = qb;
+            r.ldy = ldb;
+            r.acc = H->d_acc;
+            r.ldacc = (int64_t)D;
+            r.alpha = alpha;
+            r.beta_hi = bhi;
+            r.beta_lo = blo;
+            r.a0 = a[0];
+            r.a1 = a[1];
+            HIP_TRY(launch_reduce(r, Epi::kChebFirst, s));
+            // cur = qb (q1), prev = qa (q0)
+            float2* cur = qb;
+            int64_t ldc = ldb;
+            float2* prev = qa;
+            int64_t ldpv = lda;
+            for (int k = 1; k < K; ++k) {
+                st = run_tiles(H, cur, ldc, nv, s);
+                if (st != PROCMV_OK) return st;
+                ReduceArgs rs = reduce_args(H, nv);
+                rs.X = cur;
+                rs.ldx = ldc;
+                rs.Y = prev;   // q_{k-1} in, q_{k+1} out
+                rs.ldy = ldpv;
+                rs.acc = H->d_acc;
+                rs.ldacc = (int64_t)D;
+                rs.alpha = alpha;
+                rs.beta_hi = bhi;
+                rs.beta_lo = blo;
+                rs.a0 = a[k + 1];
+                HIP_TRY(launch_reduce(rs, Epi::kChebStep, s));
+                std::swap(cur, prev);
+                std::swap(ldc, ldpv);
+            }
+            HIP_TRY(launch_cheb_finish((int32_t)D, nv, H->d_acc, (int64_t)D, phase, P0, ld,
+                                       H->d_norm, s));
+            if (norms_out) {
+                std::vector<double> n2(nv);
+                HIP_TRY(hipMemcpyAsync(n2.data(), H->d_norm, nv * sizeof(double),
+                                       hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                for (int v = 0; v < nv; ++v)
+                    norms_out[(size_t)step * nvec + v0 + v] = std::sqrt(n2[v]);
+            }
+        }
+        v0 += nv;
+    }
+    return PROCMV_OK;
+}
+
+procmv_status procmv_get_entries(procmv_op_t H, int64_t r0, int64_t c0,
+                                 int32_t nr, int32_t nc, void* out_dev,
+                                 void* stream)
+{
+    procmv_status st = check_op(H);
+    if (st != PROCMV_OK) return st;
+    if (!out_dev) return fail(PROCMV_ERR_INVALID_ARG, "out is null");
+    if (nr < 0 || nc < 0 || r0 < 0 || c0 < 0 || r0 + nr > H->D || c0 + nc > H->D)
+        return fail(PROCMV_ERR_INVALID_ARG, "window outside the matrix");
+    if ((int64_t)nr * nc == 0) return PROCMV_OK;
+    SourceArgs src = H->source();
+    HIP_TRY(launch_get_entries(src, r0, c0, nr, nc, (float2*)out_dev, (hipStream_t)stream));
+    return PROCMV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,415 @@
+// Fused block source + two-sided block product on the VALU (gfx950).
+//
+// Paper Sec. III: phi^[n] = sum_m apply_H_block(n, m, psi^[m]) with blocks
+// that are generated on the fly or read from a cache of canonical pairs
+// (n <= m), using H^[m,n] = (H^[n,m])^dagger.  Each canonical entry is
+// obtained once and applied twice: y_i += H_ij x_j and y_j += conj(H_ij) x_i.
+//
+// Work decomposition.  The canonical upper triangle is cut into square
+// super-tiles of kSuper x kSuper; one workgroup (4 waves of 64) owns one
+// super-tile and walks its tiles of TR x 64 entries, TR = 4 * RW, each wave
+// taking RW consecutive rows and each lane one column.  Direct sums for the
+// wave's rows stay in registers across the super-tile row and are reduced
+// across lanes once; transposed sums for each lane's columns stay in
+// registers across the whole super-tile and are reduced across waves once.
+// Both go to a partial buffer in which every output element has exactly one
+// slot per super-tile band (see kSuper), and a second kernel sums the slots
+// in a fixed order: no atomics, bit-reproducible results.
+#include "kernels.h"
+
+namespace procmv {
+
+namespace {
+
+__device__ __forceinline__ float2 cmul(float2 h, float2 x)
+{
+    return make_float2(__builtin_fmaf(h.x, x.x, -h.y * x.y),
+                       __builtin_fmaf(h.x, x.y, h.y * x.x));
+}
+
+// acc += h * x
+__device__ __forceinline__ void cfma(float2& acc, float2 h, float2 x)
+{
+    acc.x = __builtin_fmaf(h.x, x.x, acc.x);
+    acc.x = __builtin_fmaf(-h.y, x.y, acc.x);
+    acc.y = __builtin_fmaf(h.x, x.y, acc.y);
+    acc.y = __builtin_fmaf(h.y, x.x, acc.y);
+}
+
+// acc += conj(h) * x
+__device__ __forceinline__ void cfma_conj(float2& acc, float2 h, float2 x)
+{
+    acc.x = __builtin_fmaf(h.x, x.x, acc.x);
+    acc.x = __builtin_fmaf(h.y, x.y, acc.x);
+    acc.y = __builtin_fmaf(h.x, x.y, acc.y);
+    acc.y = __builtin_fmaf(-h.y, x.x, acc.y);
+}
+
+// acc += r * x (real entry)
+__device__ __forceinline__ void rfma(float2& acc, float r, float2 x)
+{
+    acc.x = __builtin_fmaf(r, x.x, acc.x);
+    acc.y = __builtin_fmaf(r, x.y, acc.y);
+}
+
+// Sum over the 64 lanes of a wave of N = 32 values per lane.  Butterfly
+// reduce-scatter: after it, lanes l and l^1 both hold the wave total of value
+// index l >> 1.
+__device__ __forceinline__ float wave_reduce_scatter32(float (&v)[32])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        bool up = lane & 32;
+        float keep = up ? v[16 + k] : v[k];
+        float give = up ? v[k] : v[16 + k];
+        v[k] = keep + __shfl_xor(give, 32);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        bool up = lane & 16;
+        float keep = up ? v[8 + k] : v[k];
+        float give = up ? v[k] : v[8 + k];
+        v[k] = keep + __shfl_xor(give, 16);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        bool up = lane & 8;
+        float keep = up ? v[4 + k] : v[k];
+        float give = up ? v[k] : v[4 + k];
+        v[k] = keep + __shfl_xor(give, 8);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        bool up = lane & 4;
+        float keep = up ? v[2 + k] : v[k];
+        float give = up ? v[k] : v[2 + k];
+        v[k] = keep + __shfl_xor(give, 4);
+    }
+    {
+        bool up = lane & 2;
+        float keep = up ? v[1] : v[0];
+        float give = up ? v[0] : v[1];
+        v[0] = keep + __shfl_xor(give, 2);
+    }
+    return v[0] + __shfl_xor(v[0], 1);
+}
+
+// Block pair slot of the tile whose first row/column are (i0, j0).
+__device__ __forceinline__ int32_t tile_slot(const SourceArgs& s, int i0, int j0)
+{
+    if (s.pair_slot == nullptr) return -1;
+    int n = i0 / s.b, m = j0 / s.b;
+    return s.pair_slot[n * s.n_blk + m];
+}
+
+template <int NV, int RW, int GEN>
+__global__ __launch_bounds__(256) void tile_apply_kernel(TileArgs a)
+{
+    constexpr int TR = 4 * RW;          // rows per tile
+    constexpr int SR = kSuper / TR;     // row tiles per super-tile
+    constexpr int SC = kSuper / 64;     // column tiles per super-tile
+    static_assert(RW * NV == 16, "register budget assumes RW * NV == 16");
+
+    __shared__ float2 red[4][64][NV];
+
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int2 st = a.st_list[blockIdx.x];
+    const int sr = st.x, sc = st.y;
+    const bool diag_st = (sr == sc);
+    const int row0 = sr * kSuper, col0 = sc * kSuper;
+    const int D = a.D;
+
+    float2 tr[SC][NV];
+#pragma unroll
+    for (int c = 0; c < SC; ++c)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) tr[c][v] = make_float2(0.f, 0.f);
+
+    for (int rr = 0; rr < SR; ++rr) {
+        const int trow0 = row0 + rr * TR;   // first row of the tile (WG-uniform)
+        const int ib = trow0 + w * RW;      // first row of this wave
+        float2 dir[RW][NV];
+        float2 xi[RW][NV];
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                dir[r][v] = make_float2(0.f, 0.f);
+                int i = ib + r;
+                xi[r][v] = (i < D) ? a.X[v * a.ldx + i] : make_float2(0.f, 0.f);
+            }
+
+#pragma unroll
+        for (int cc = 0; cc < SC; ++cc) {
+            const int tcol0 = col0 + cc * 64;
+            if (trow0 >= D || tcol0 >= D) continue;
+            // tiles strictly below the diagonal belong to the transpose
+            if (diag_st && rr * TR > cc * 64 + 63) continue;
+            const int j = tcol0 + lane;
+            const bool jin = j < D;
+            float2 xj[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                xj[v] = jin ? a.X[v * a.ldx + j] : make_float2(0.f, 0.f);
+
+            const int32_t slot = tile_slot(a.src, trow0, tcol0);
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const int i = ib + r;
+                const bool ok = jin && (i < D) && (i <= j);
+                const bool upper = ok && (i < j);
+                if (GEN == 0) {
+                    float2 h;
+                    if (slot >= 0) {
+                        const float2* sp = (const float2*)a.src.slots +
+                                           (size_t)slot * a.src.b * a.src.b;
+                        const int ii = i - (trow0 / a.src.b) * a.src.b;
+                        const int jj = j - (tcol0 / a.src.b) * a.src.b;
+                        h = ok ? sp[(size_t)ii * a.src.b + jj] : make_float2(0.f, 0.f);
+                    } else {
+                        const uint32_t ic = ok ? (uint32_t)i : 0u;
+                        const uint32_t jc = ok ? (uint32_t)j : 1u;
+                        uint32_t x0, x1;
+                        philox_ij(ic, jc, a.src.gue.k0, a.src.gue.k1, x0, x1);
+                        float z0, z1;
+                        box_muller(x0, x1, z0, z1);
+                        h = (i == j) ? make_float2(a.src.gue.s_diag * z0, 0.f)
+                                     : make_float2(a.src.gue.s_off * z0, a.src.gue.s_off * z1);
+                    }
+                    if (!ok) h = make_float2(0.f, 0.f);
+                    const float2 ht = upper ? h : make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        cfma(dir[r][v], h, xj[v]);
+                        cfma_conj(tr[cc][v], ht, xi[r][v]);
+                    }
+                } else {
+                    float hv;
+                    if (slot >= 0) {
+                        const float* sp = (const float*)a.src.slots +
+                                          (size_t)slot * a.src.b * a.src.b;
+                        const int ii = i - (trow0 / a.src.b) * a.src.b;
+                        const int jj = j - (tcol0 / a.src.b) * a.src.b;
+                        hv = ok ? sp[(size_t)ii * a.src.b + jj] : 0.f;
+                    } else {
+                        hv = ok ? dvr_entry(a.src.dvr, (uint32_t)i, (uint32_t)j) : 0.f;
+                    }
+                    const float hvt = upper ? hv : 0.f;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        rfma(dir[r][v], hv, xj[v]);
+                        rfma(tr[cc][v], hvt, xi[r][v]);
+                    }
+                }
+            }
+        }
+
+        // Direct partial of this tile row: reduce over the 64 lanes (columns),
+        // slot sc.  Value index (v * RW + r) * 2 + {re, im}.
+        float vals[32];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                vals[(v * RW + r) * 2 + 0] = dir[r][v].x;
+                vals[(v * RW + r) * 2 + 1] = dir[r][v].y;
+            }
+        const float tot = wave_reduce_scatter32(vals);
+        if ((lane & 1) == 0) {
+            const int idx = lane >> 1;
+            const int comp = idx & 1;
+            const int r = (idx >> 1) % RW;
+            const int v = (idx >> 1) / RW;
+            const int i = ib + r;
+            if (i < D) {
+                float* p = (float*)(a.P + ((size_t)sc * NV + v) * a.ldp + i);
+                p[comp] = tot;
+            }
+        }
+    }
+
+    // Transposed partials: reduce over the 4 waves (rows), slot sr, or N_s for
+    // the diagonal super-tile.
+    const int slot_t = diag_st ? a.n_super : sr;
+#pragma unroll
+    for (int cc = 0; cc < SC; ++cc) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) red[w][lane][v] = tr[cc][v];
+        __syncthreads();
+        if (w == 0) {
+            const int j = col0 + cc * 64 + lane;
+            if (j < D) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    float2 s = red[0][lane][v];
+                    s.x += red[1][lane][v].x; s.y += red[1][lane][v].y;
+                    s.x += red[2][lane][v].x; s.y += red[2][lane][v].y;
+                    s.x += red[3][lane][v].x; s.y += red[3][lane][v].y;
+                    a.P[((size_t)slot_t * NV + v) * a.ldp + j] = s;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <Epi MODE>
+__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)a.nv * a.D;
+    if (t >= total) return;
+    const int v = (int)(t / a.D);
+    const int i = (int)(t - (int64_t)v * a.D);
+    float sx = 0.f, sy = 0.f;
+    const float2* p = a.P + (size_t)v * a.ldp + i;
+    const size_t stride = (size_t)a.nv * a.ldp;
+    for (int k = 0; k < a.n_slots; ++k) {
+        float2 q = p[k * stride];
+        sx += q.x;
+        sy += q.y;
+    }
+    const float2 x = a.X[v * a.ldx + i];
+    // h = alpha * y + (beta_hi + beta_lo) * x
+    const float bx = __builtin_fmaf(a.beta_hi, x.x, a.beta_lo * x.x);
+    const float by = __builtin_fmaf(a.beta_hi, x.y, a.beta_lo * x.y);
+    const float hx = __builtin_fmaf(a.alpha, sx, bx);
+    const float hy = __builtin_fmaf(a.alpha, sy, by);
+    if (MODE == Epi::kApply) {
+        a.Y[v * a.ldy + i] = make_float2(hx, hy);
+    } else if (MODE == Epi::kChebFirst) {
+        a.Yq1[v * a.ldy + i] = make_float2(hx, hy);
+        // acc = a0 q0 + a1 q1
+        double2 r;
+        r.x = a.a0.x * (double)x.x - a.a0.y * (double)x.y;
+        r.y = a.a0.x * (double)x.y + a.a0.y * (double)x.x;
+        r.x += a.a1.x * (double)hx - a.a1.y * (double)hy;
+        r.y += a.a1.x * (double)hy + a.a1.y * (double)hx;
+        a.acc[v * a.ldacc + i] = r;
+    } else {
+        float2* qp = a.Y + v * a.ldy + i;
+        const float2 prev = *qp;
+        const float nx = __builtin_fmaf(2.0f, hx, -prev.x);
+        const float ny = __builtin_fmaf(2.0f, hy, -prev.y);
+        *qp = make_float2(nx, ny);
+        double2 r = a.acc[v * a.ldacc + i];
+        r.x += a.a0.x * (double)nx - a.a0.y * (double)ny;
+        r.y += a.a0.x * (double)ny + a.a0.y * (double)nx;
+        a.acc[v * a.ldacc + i] = r;
+    }
+}
+
+template <int GEN>
+__global__ void cache_fill_kernel(SourceArgs s, int32_t D, const int2* pairs,
+                                  int64_t n_pairs, void* slots)
+{
+    const int64_t bb = (int64_t)s.b * s.b;
+    const int64_t total = n_pairs * bb;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = t / bb;
+        const int64_t e = t - p * bb;
+        const int ii = (int)(e / s.b), jj = (int)(e - (int64_t)ii * s.b);
+        const int2 nm = pairs[p];
+        const int64_t i = (int64_t)nm.x * s.b + ii, j = (int64_t)nm.y * s.b + jj;
+        const bool in = i < D && j < D;
+        if (GEN == 0) {
+            float2 h = in ? gue_entry(s.gue, (uint32_t)i, (uint32_t)j) : make_float2(0.f, 0.f);
+            ((float2*)slots)[t] = h;
+        } else {
+            float h = in ? dvr_entry(s.dvr, (uint32_t)i, (uint32_t)j) : 0.f;
+            ((float*)slots)[t] = h;
+        }
+    }
+}
+
+template <int GEN>
+__global__ void get_entries_kernel(SourceArgs s, int64_t r0, int64_t c0,
+                                   int32_t nr, int32_t nc, float2* out)
+{
+    const int64_t total = (int64_t)nr * nc;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = t / nc, b = t - a * nc;
+        const uint32_t i = (uint32_t)(r0 + a), j = (uint32_t)(c0 + b);
+        if (GEN == 0) out[t] = gue_entry(s.gue, i, j);
+        else out[t] = make_float2(dvr_entry(s.dvr, i, j), 0.f);
+    }
+}
+
+template <int NV, int RW>
+hipError_t launch_nv(const TileArgs& a, int n_st, hipStream_t s)
+{
+    if (a.src.gen == 0)
+        hipLaunchKernelGGL((tile_apply_kernel<NV, RW, 0>), dim3(n_st), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((tile_apply_kernel<NV, RW, 1>), dim3(n_st), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_tile_apply(const TileArgs& a, int nv, int n_st, hipStream_t s)
+{
+    switch (nv) {
+    case 1: return launch_nv<1, 16>(a, n_st, s);
+    case 2: return launch_nv<2, 8>(a, n_st, s);
+    case 4: return launch_nv<4, 4>(a, n_st, s);
+    case 8: return launch_nv<8, 2>(a, n_st, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, Epi mode, hipStream_t s)
+{
+    const int64_t total = (int64_t)a.nv * a.D;
+    const dim3 grid((unsigned)((total + 255) / 256));
+    switch (mode) {
+    case Epi::kApply:
+        hipLaunchKernelGGL(reduce_kernel<Epi::kApply>, grid, dim3(256), 0, s, a);
+        break;
+    case Epi::kChebFirst:
+        hipLaunchKernelGGL(reduce_kernel<Epi::kChebFirst>, grid, dim3(256), 0, s, a);
+        break;
+    case Epi::kChebStep:
+        hipLaunchKernelGGL(reduce_kernel<Epi::kChebStep>, grid, dim3(256), 0, s, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cache_fill(const SourceArgs& src, int32_t D, const int2* pairs,
+                             int64_t n_pairs, void* slots, hipStream_t s)
+{
+    const int64_t total = n_pairs * (int64_t)src.b * src.b;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    if (src.gen == 0)
+        hipLaunchKernelGGL(cache_fill_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           src, D, pairs, n_pairs, slots);
+    else
+        hipLaunchKernelGGL(cache_fill_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           src, D, pairs, n_pairs, slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_entries(const SourceArgs& src, int64_t r0, int64_t c0,
+                              int32_t nr, int32_t nc, float2* out, hipStream_t s)
+{
+    const int64_t total = (int64_t)nr * nc;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    if (src.gen == 0)
+        hipLaunchKernelGGL(get_entries_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           src, r0, c0, nr, nc, out);
+    else
+        hipLaunchKernelGGL(get_entries_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           src, r0, c0, nr, nc, out);
+    return hipGetLastError();
+}
+
+}  // namespace procmv

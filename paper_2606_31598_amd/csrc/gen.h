@@ -1,0 +1,173 @@
+// Device-side block sources: Philox-GUE entries and sinc-DVR entries.
+//
+// Seeded generation (paper Sec. III) keyed on global (i, j) so the operator
+// does not depend on the block partition (Sec. II).  The binary32 Gaussian
+// transform below is a fixed sequence of IEEE operations (explicit fmaf, no
+// contraction, correctly rounded division and square root), so the entries
+// are reproducible bit for bit by any faithful implementation of the same
+// definition.  Translation units including this header are built with
+// -ffp-contract=off.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace procmv {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): two 32x32->64
+// multiplications per round, Weyl key schedule.
+struct Philox {
+    static constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    static constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+};
+
+__device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1,
+                                             uint32_t& c2, uint32_t& c3,
+                                             uint32_t k0, uint32_t k1)
+{
+    uint64_t p0 = (uint64_t)Philox::M0 * c0;
+    uint64_t p1 = (uint64_t)Philox::M1 * c2;
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+}
+
+// Words 0 and 1 of Philox4x32-10 at counter (i, j, 0, 0).
+__device__ __forceinline__ void philox_ij(uint32_t i, uint32_t j, uint32_t k0,
+                                          uint32_t k1, uint32_t& x0,
+                                          uint32_t& x1)
+{
+    uint32_t c0 = i, c1 = j, c2 = 0u, c3 = 0u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        philox_round(c0, c1, c2, c3, k0, k1);
+        k0 += Philox::W0;
+        k1 += Philox::W1;
+    }
+    x0 = c0;
+    x1 = c1;
+}
+
+// Uniform (2 (x >> 9) + 1) 2^-24 in (0, 1), exact in binary32.
+__device__ __forceinline__ float u01(uint32_t x)
+{
+    return (float)((x >> 9) * 2u + 1u) * 5.9604644775390625e-8f;
+}
+
+// ln u for u in (0, 1): u = 2^e m with m in [sqrt(1/2), sqrt(2)];
+// ln m = 2 atanh(s), s = (m - 1)/(m + 1), odd series through s^9.
+__device__ __forceinline__ float ln_unit(float u)
+{
+    uint32_t b = __float_as_uint(u);
+    int e = (int)(b >> 23) - 127;
+    float m = __uint_as_float((b & 0x007FFFFFu) | 0x3F800000u);
+    if (m > 1.41421356237309504880f) {
+        m = m * 0.5f;
+        e = e + 1;
+    }
+    float f = m - 1.0f;
+    float s = f / (2.0f + f);
+    float s2 = s * s;
+    float p = __builtin_fmaf(s2, (float)(2.0 / 9.0), (float)(2.0 / 7.0));
+    p = __builtin_fmaf(s2, p, (float)(2.0 / 5.0));
+    p = __builtin_fmaf(s2, p, (float)(2.0 / 3.0));
+    float lm = __builtin_fmaf(s * s2, p, 2.0f * s);
+    float ef = (float)e;
+    const float ln2_hi = 0.693147180559945309417f;
+    const float ln2_lo = (float)(0.693147180559945309417232121458 -
+                                 (double)0.693147180559945309417f);
+    return __builtin_fmaf(ef, ln2_hi, __builtin_fmaf(ef, ln2_lo, lm));
+}
+
+// sin(2 pi u), cos(2 pi u): exact quarter-turn reduction u = n/4 + r,
+// |r| <= 1/8, then the Taylor polynomials of sin(2 pi r) through r^9 and of
+// cos(2 pi r) through r^10 (coefficients (2 pi)^k / k!).
+__device__ __forceinline__ void sincos_turn(float u, float& sv, float& cv)
+{
+    float n = __builtin_rintf(4.0f * u);
+    float r = __builtin_fmaf(n, -0.25f, u);
+    float r2 = r * r;
+    float ps = __builtin_fmaf(r2, 42.0586939448976531450f, -76.7058597530613858416f);
+    ps = __builtin_fmaf(r2, ps, 81.6052492760750542034f);
+    ps = __builtin_fmaf(r2, ps, -41.3417022403997602340f);
+    ps = __builtin_fmaf(r2, ps, 6.28318530717958647692f);
+    float sr = r * ps;
+    float pc = __builtin_fmaf(r2, -26.4262567833743974529f, 60.2446413718766603627f);
+    pc = __builtin_fmaf(r2, pc, -85.4568172066937277360f);
+    pc = __builtin_fmaf(r2, pc, 64.9393940226682914910f);
+    pc = __builtin_fmaf(r2, pc, -19.7392088021787172377f);
+    float cr = __builtin_fmaf(r2, pc, 1.0f);
+    int q = ((int)n) & 3;
+    float s0 = (q & 1) ? cr : sr;
+    float c0 = (q & 1) ? sr : cr;
+    sv = (q & 2) ? -s0 : s0;
+    cv = ((q + 1) & 2) ? -c0 : c0;
+}
+
+// Box-Muller: z0 = r cos(2 pi u1), z1 = r sin(2 pi u1), r = sqrt(-2 ln u0).
+__device__ __forceinline__ void box_muller(uint32_t x0, uint32_t x1, float& z0,
+                                           float& z1)
+{
+    float l = ln_unit(u01(x0));
+    float r = __builtin_sqrtf(-2.0f * l);
+    float sv, cv;
+    sincos_turn(u01(x1), sv, cv);
+    z0 = r * cv;
+    z1 = r * sv;
+}
+
+// Parameters of the Philox-GUE source.
+struct GueParams {
+    uint32_t k0, k1;      // key = (seed low, seed high)
+    float s_off, s_diag;  // binary32 scales sqrt(1/(2D)), sqrt(1/D)
+};
+
+// Canonical entry H_ij, i < j.
+__device__ __forceinline__ float2 gue_upper(const GueParams& g, uint32_t i,
+                                            uint32_t j)
+{
+    uint32_t x0, x1;
+    philox_ij(i, j, g.k0, g.k1, x0, x1);
+    float z0, z1;
+    box_muller(x0, x1, z0, z1);
+    return make_float2(g.s_off * z0, g.s_off * z1);
+}
+
+// Diagonal entry H_ii (real).
+__device__ __forceinline__ float gue_diag(const GueParams& g, uint32_t i)
+{
+    uint32_t x0, x1;
+    philox_ij(i, i, g.k0, g.k1, x0, x1);
+    float z0, z1;
+    box_muller(x0, x1, z0, z1);
+    return g.s_diag * z0;
+}
+
+// Any entry H_ij (conjugated canonical draw below the diagonal).
+__device__ __forceinline__ float2 gue_entry(const GueParams& g, uint32_t i,
+                                            uint32_t j)
+{
+    if (i == j) return make_float2(gue_diag(g, i), 0.0f);
+    if (i < j) return gue_upper(g, i, j);
+    float2 h = gue_upper(g, j, i);
+    return make_float2(h.x, -h.y);
+}
+
+// Parameters of the sinc-DVR source: binary32 kinetic symbol tk[k] for
+// k = |i - j| >= 1 and binary32 potential v[i]; the binary64 constant
+// diagonal is applied in the reduction epilogue.
+struct DvrParams {
+    const float* tk;
+    const float* v;
+};
+
+__device__ __forceinline__ float dvr_entry(const DvrParams& p, uint32_t i,
+                                           uint32_t j)
+{
+    if (i == j) return p.v[i];
+    return p.tk[i > j ? i - j : j - i];
+}
+
+}  // namespace procmv

@@ -1,0 +1,82 @@
+// Kernel launch descriptors shared by the kernel files and the host API.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gen.h"
+
+namespace procmv {
+
+// Square super-tile edge of the VALU tile kernel.  Output element i of band
+// B = i / kSuper receives exactly one partial per slot k in [0, N_s]:
+// slot k >= B from the direct product of super-tile (B, k), slot k < B from
+// the transposed product of super-tile (k, B), slot N_s from the transposed
+// product of the diagonal super-tile (B, B).
+constexpr int kSuper = 256;
+
+// Where the entries of one tile come from.
+struct SourceArgs {
+    int gen;                   // 0 Philox-GUE, 1 sinc-DVR
+    GueParams gue;
+    DvrParams dvr;
+    const int32_t* pair_slot;  // [n_blk * n_blk] slot of canonical pair or -1; null = no cache
+    const void* slots;         // slot pool: b*b complex64 (GUE) or float (DVR) per slot
+    int32_t b;
+    int32_t n_blk;
+};
+
+struct TileArgs {
+    SourceArgs src;
+    int32_t D;
+    int32_t n_super;          // N_s = ceil(D / kSuper)
+    const int2* st_list;      // super-tile coordinates (sr, sc), sr <= sc
+    const float2* X;          // nvec-chunk base, vector v at X + v * ldx
+    int64_t ldx;
+    float2* P;                // partials: slot s, vector v at P + (s * nv + v) * ldp
+    int64_t ldp;
+};
+
+// Epilogue of the fixed-order partial reduction.
+enum class Epi : int {
+    kApply = 0,     // Y = alpha y + beta x
+    kChebFirst = 1, // q1 = h;              acc = a0 q0 + a1 q1
+    kChebStep = 2   // qn = 2 h - q_prev;   acc += a qn   (qn stored over q_prev)
+};
+
+struct ReduceArgs {
+    int32_t D;
+    int32_t nv;
+    int32_t n_slots;          // N_s + 1
+    const float2* P;
+    int64_t ldp;
+    const float2* X;          // the vectors the product was applied to
+    int64_t ldx;
+    float2* Y;                // kApply: output; kChebStep: q_prev in, q_next out
+    int64_t ldy;
+    float2* Yq1;              // kChebFirst: q1 out
+    double2* acc;             // binary64 accumulator (nv, ldacc)
+    int64_t ldacc;
+    float alpha;              // 1/R (Chebyshev) or 1 (apply)
+    float beta_hi, beta_lo;   // constant-diagonal term, hi + lo binary32 pair
+    double2 a0, a1;           // Chebyshev coefficients of the epilogue
+};
+
+// Launchers (defined in apply.hip).
+hipError_t launch_tile_apply(const TileArgs& a, int nv, int n_st,
+                             hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs& a, Epi mode, hipStream_t s);
+hipError_t launch_cache_fill(const SourceArgs& src, int32_t D,
+                             const int2* pairs, int64_t n_pairs, void* slots,
+                             hipStream_t s);
+hipError_t launch_get_entries(const SourceArgs& src, int64_t r0, int64_t c0,
+                              int32_t nr, int32_t nc, float2* out,
+                              hipStream_t s);
+// Chebyshev helpers (defined in cheb.hip).
+hipError_t launch_cheb_finish(int32_t D, int32_t nv, const double2* acc,
+                              int64_t ldacc, double2 phase, float2* psi,
+                              int64_t ld, double* norm2, hipStream_t s);
+hipError_t launch_copy_vectors(int32_t D, int32_t nv, const float2* src,
+                               int64_t lds, float2* dst, int64_t ldd,
+                               hipStream_t s);
+
+}  // namespace procmv

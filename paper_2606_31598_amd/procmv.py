@@ -1,0 +1,203 @@
+"""Thin ctypes binding of libprocmv.so (argument marshalling only).
+
+Every step of the products and the propagation runs in the library's HIP
+kernels; PyTorch only provides device memory and the current stream.  If the
+library is missing, loading fails loudly: there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libprocmv.so")
+
+GEN_PHILOX_GUE = 0
+GEN_SINC_DVR = 1
+PROCEDURAL, PARTIAL, FULL = 0, 1, 2
+FP32, SPLIT_BF16 = 0, 1
+
+_STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "INFEASIBLE_PLAN",
+           4: "NOT_PLANNED", 5: "HIP", 6: "INTERNAL"}
+
+EXPORTS = [
+    "procmv_create_operator", "procmv_plan", "procmv_apply",
+    "procmv_spectral_bounds", "procmv_cheb_order",
+    "procmv_chebyshev_propagate", "procmv_get_entries", "procmv_plan_info",
+    "procmv_destroy", "procmv_last_error",
+]
+
+
+class ProcmvError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"procmv {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class DvrParams(ctypes.Structure):
+    _fields_ = [("x_min", ctypes.c_double), ("x_max", ctypes.c_double),
+                ("mass", ctypes.c_double), ("omega", ctypes.c_double),
+                ("compensate", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int64), ("block_size", ctypes.c_int32),
+                ("n_blk", ctypes.c_int32), ("n_pair", ctypes.c_int64),
+                ("p_cache", ctypes.c_int64), ("cache_bytes", ctypes.c_int64),
+                ("work_bytes", ctypes.c_int64), ("strategy", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libprocmv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2606_31598_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    c = ctypes
+    vp = c.c_void_p
+    L.procmv_create_operator.argtypes = [c.c_int, c.c_uint64, c.c_int64, vp,
+                                         c.POINTER(vp)]
+    L.procmv_plan.argtypes = [vp, c.c_int32, c.c_int, c.c_double, c.c_int, vp]
+    L.procmv_apply.argtypes = [vp, vp, c.c_int64, vp, c.c_int64, c.c_int32, vp]
+    L.procmv_spectral_bounds.argtypes = [vp, c.POINTER(c.c_double),
+                                         c.POINTER(c.c_double)]
+    L.procmv_cheb_order.argtypes = [c.c_double, c.c_double]
+    L.procmv_cheb_order.restype = c.c_int32
+    L.procmv_chebyshev_propagate.argtypes = [vp, vp, c.c_int64, c.c_int32,
+                                             c.c_double, c.c_int32, c.c_int32,
+                                             c.c_double, c.c_double,
+                                             c.POINTER(c.c_double), vp]
+    L.procmv_get_entries.argtypes = [vp, c.c_int64, c.c_int64, c.c_int32,
+                                     c.c_int32, vp, vp]
+    L.procmv_plan_info.argtypes = [vp, c.POINTER(PlanInfo)]
+    L.procmv_destroy.argtypes = [vp]
+    L.procmv_destroy.restype = None
+    L.procmv_last_error.restype = c.c_char_p
+    for name in EXPORTS:
+        if name in ("procmv_cheb_order", "procmv_destroy", "procmv_last_error"):
+            continue
+        getattr(L, name).restype = c.c_int
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != 0:
+        raise ProcmvError(status, load().procmv_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _vec_arg(t, D):
+    """(pointer, leading dimension, nvec) of a (nvec, D) complex64 CUDA tensor."""
+    import torch
+    if t.dtype != torch.complex64 or not t.is_cuda:
+        raise TypeError("vectors must be complex64 CUDA tensors")
+    if t.dim() == 1:
+        t = t.unsqueeze(0)
+    if t.dim() != 2 or t.shape[1] != D or t.stride(1) != 1:
+        raise ValueError(f"expected shape (nvec, {D}) with unit column stride")
+    return ctypes.c_void_p(t.data_ptr()), t.stride(0) if t.shape[0] > 1 else D, t.shape[0]
+
+
+def cheb_order(x: float, tol: float = 1e-10) -> int:
+    return int(load().procmv_cheb_order(float(x), float(tol)))
+
+
+class Operator:
+    """A dense Hermitian operator applied without materialising its matrix."""
+
+    def __init__(self, gen, D, seed=0, x_min=-20.0, x_max=20.0, mass=1.0,
+                 omega=1.0, compensate=True):
+        L = load()
+        self.D = int(D)
+        self.gen = gen
+        h = ctypes.c_void_p()
+        params = None
+        if gen == GEN_SINC_DVR:
+            self._params = DvrParams(x_min, x_max, mass, omega, 1 if compensate else 0)
+            params = ctypes.byref(self._params)
+        _check(L.procmv_create_operator(gen, ctypes.c_uint64(seed), self.D,
+                                        params, ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def gue(cls, D, seed):
+        return cls(GEN_PHILOX_GUE, D, seed=seed)
+
+    @classmethod
+    def dvr(cls, D, **kw):
+        return cls(GEN_SINC_DVR, D, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().procmv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def plan(self, block_size=256, strategy=PROCEDURAL, cache_fraction=0.0,
+             precision=FP32, stream=None):
+        _check(load().procmv_plan(self._h, int(block_size), int(strategy),
+                                  float(cache_fraction), int(precision),
+                                  _stream(stream)))
+        return self
+
+    def plan_info(self) -> dict:
+        info = PlanInfo()
+        _check(load().procmv_plan_info(self._h, ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in PlanInfo._fields_}
+
+    def apply(self, X, Y=None, stream=None):
+        """Y = H X for a (nvec, D) complex64 CUDA tensor X."""
+        import torch
+        px, ldx, nv = _vec_arg(X, self.D)
+        if Y is None:
+            Y = torch.empty((nv, self.D), dtype=torch.complex64, device=X.device)
+        py, ldy, nvy = _vec_arg(Y, self.D)
+        if nvy != nv:
+            raise ValueError("X and Y hold different numbers of vectors")
+        _check(load().procmv_apply(self._h, px, ldx, py, ldy, nv, _stream(stream)))
+        return Y
+
+    def spectral_bounds(self):
+        c = ctypes.c_double()
+        R = ctypes.c_double()
+        _check(load().procmv_spectral_bounds(self._h, ctypes.byref(c), ctypes.byref(R)))
+        return c.value, R.value
+
+    def propagate(self, psi, dt, nsteps=1, K=0, c=0.0, R=0.0, norms=False,
+                  stream=None):
+        """psi <- exp(-i H dt)^nsteps psi in place (Chebyshev); returns the
+        (nsteps, nvec) binary64 norms when ``norms``."""
+        pp, ld, nv = _vec_arg(psi, self.D)
+        out = np.zeros((max(nsteps, 1), nv), np.float64) if norms else None
+        optr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if norms else None
+        _check(load().procmv_chebyshev_propagate(
+            self._h, pp, ld, nv, float(dt), int(K), int(nsteps), float(c),
+            float(R), optr, _stream(stream)))
+        return out
+
+    def entries(self, r0, c0, nr, nc, stream=None):
+        """Generated binary32 entries of a window, as a complex64 CUDA tensor."""
+        import torch
+        out = torch.empty((nr, nc), dtype=torch.complex64, device="cuda")
+        _check(load().procmv_get_entries(self._h, int(r0), int(c0), int(nr),
+                                         int(nc), ctypes.c_void_p(out.data_ptr()),
+                                         _stream(stream)))
+        return out

@@ -1,0 +1,142 @@
+"""GPU parity: generated entries and products against the binary64 oracle.
+
+Entries must match the oracle's generator bit for bit; products must be
+within rel-L2 1e-5 of the binary64 product (FP32 arithmetic), and every
+storage mode must give bit-identical products for the same input.
+"""
+import numpy as np
+import pytest
+
+from paper_2606_31598_amd import workloads
+from tests.gpu_util import rel_l2, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_31598_amd import procmv
+    procmv.load()
+    return procmv
+
+
+@pytest.mark.parametrize("D,win", [
+    (2048, (0, 0, 256, 256)), (2048, (1700, 100, 348, 333)),
+    (1000, (0, 0, 1000, 1000)), (262144, (262000, 100, 144, 200)),
+    (262144, (5, 131072, 64, 300))])
+def test_gue_entries_bit_exact(pm, orc, D, win):
+    r0, c0, nr, nc = win
+    op = pm.Operator.gue(D, seed=1)
+    got = to_host(op.entries(r0, c0, nr, nc))
+    want = orc.gue_entries(1, r0, c0, nr, nc, D=D)
+    assert got.dtype == np.complex64
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_dvr_entries_bit_exact(pm, orc):
+    D = 4096
+    op = pm.Operator.dvr(D)
+    d = orc.DVR(D)
+    got = to_host(op.entries(0, 0, 300, 4096))
+    idx_i = np.arange(300)[:, None]
+    idx_j = np.arange(4096)[None, :]
+    want = d.tk32[np.abs(idx_i - idx_j)]
+    want[np.arange(300), np.arange(300)] = d.v32[:300]
+    assert np.array_equal(got.real, want) and np.all(got.imag == 0)
+
+
+def test_c0_ten_repeated_matvecs(pm, orc):
+    """D = 2048 GUE, b = 256, procedural, psi = normalised Gaussian seed 2."""
+    D = 2048
+    op = pm.Operator.gue(D, seed=1).plan(256, pm.PROCEDURAL)
+    psi = workloads.gaussian_vectors(D, 1, seed=2)
+    ref = orc.gue_apply_rows(1, D, psi)
+    X = to_dev(psi)
+    outs = [to_host(op.apply(X)) for _ in range(10)]
+    for o in outs:
+        assert rel_l2(o, ref) <= TOL_FP32
+        assert np.array_equal(o, outs[0])
+    # chained H^3 psi against the oracle chain
+    Y = X
+    R = psi
+    for _ in range(3):
+        Y = op.apply(Y)
+        R = orc.gue_apply_rows(1, D, R)
+    assert rel_l2(to_host(Y), R) <= 3 * TOL_FP32
+
+
+@pytest.mark.parametrize("D,nvec,b", [(1, 1, 64), (65, 3, 64), (777, 5, 128),
+                                      (1000, 11, 256), (4096, 4, 512),
+                                      (3001, 16, 1024)])
+def test_gue_ragged_and_multivector(pm, orc, D, nvec, b):
+    op = pm.Operator.gue(D, seed=7).plan(b, pm.PROCEDURAL)
+    X = workloads.gaussian_vectors(D, nvec, seed=D + nvec)
+    got = to_host(op.apply(to_dev(X)))
+    ref = orc.gue_apply_rows(7, D, X)
+    assert rel_l2(got, ref) <= TOL_FP32
+
+
+@pytest.mark.parametrize("gen", ["gue", "dvr"])
+def test_storage_modes_bit_identical(pm, orc, gen):
+    D = 1500
+    X = to_dev(workloads.gaussian_vectors(D, 4, seed=3))
+    outs = []
+    for strat, f in [(pm.PROCEDURAL, 0.0), (pm.PARTIAL, 0.5), (pm.PARTIAL, 0.25),
+                     (pm.FULL, 1.0)]:
+        for b in (128, 512):
+            op = pm.Operator.gue(D, seed=4) if gen == "gue" else pm.Operator.dvr(D)
+            op.plan(b, strat, f)
+            info = op.plan_info()
+            if strat == pm.FULL:
+                assert info["p_cache"] == info["n_pair"]
+            if strat == pm.PARTIAL:
+                assert info["p_cache"] == int(np.floor(f * info["n_pair"]))
+            outs.append(to_host(op.apply(X)))
+            op.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    Xh = workloads.gaussian_vectors(D, 4, seed=3)
+    ref = orc.gue_apply_rows(4, D, Xh) if gen == "gue" else orc.DVR(D).apply_rows(Xh)
+    assert rel_l2(outs[0], ref) <= TOL_FP32
+
+
+def test_dvr_apply_random_vectors(pm, orc):
+    D = 8192
+    op = pm.Operator.dvr(D).plan(256, pm.PROCEDURAL)
+    X = workloads.gaussian_vectors(D, 2, seed=9)
+    got = to_host(op.apply(to_dev(X)))
+    ref = orc.DVR(D).apply_rows(X)
+    assert rel_l2(got, ref) <= TOL_FP32
+
+
+def test_hermitian_identity_on_gpu(pm):
+    D = 3000
+    op = pm.Operator.gue(D, seed=11).plan(256)
+    x = workloads.gaussian_vectors(D, 1, seed=1)
+    y = workloads.gaussian_vectors(D, 1, seed=2)
+    Hx = to_host(op.apply(to_dev(x)))[0].astype(np.complex128)
+    Hy = to_host(op.apply(to_dev(y)))[0].astype(np.complex128)
+    xs = x[0].astype(np.complex64).astype(np.complex128)
+    ys = y[0].astype(np.complex64).astype(np.complex128)
+    assert abs(np.vdot(xs, Hy) - np.vdot(Hx, ys)) < 1e-5
+
+
+def test_errors_reported(pm):
+    import torch
+    op = pm.Operator.gue(512, seed=1)
+    X = torch.zeros((1, 512), dtype=torch.complex64, device="cuda")
+    with pytest.raises(pm.ProcmvError) as e:
+        op.apply(X)
+    assert e.value.status == 4
+    op.plan(64)
+    with pytest.raises(pm.ProcmvError) as e:
+        op.apply(X, X)
+    assert e.value.status == 1
+    with pytest.raises(pm.ProcmvError) as e:
+        op.plan(64, pm.FULL, precision=7)
+    assert e.value.status == 1
