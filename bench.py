@@ -1,0 +1,216 @@
+"""Benchmark: Gelem/s of H applied and Chebyshev steps/s on one MI355X.
+
+Default workload: sinc-DVR harmonic oscillator, D = 32768 on x in [-20, 20],
+wavepacket at x0 = 3 (sigma = 1), Chebyshev propagation with dt = 0.05 and
+the order from the Bessel-coefficient rule.  One benchmark step is one
+Chebyshev time step: K + 1 coefficient terms, K products H q (each one
+generated-block product over all D^2 entries plus its fixed-order reduction
+with the recurrence and the binary64 accumulation fused), and the final
+rounding and binary64 norm.
+
+The JSON line reports the whole-step throughput in matrix elements applied
+per second, the throughput of each storage mode (procedural, 50% partial
+cache, full cache) for single products, the roofline position of the
+dominant kernel (from HIP events recorded around sampled launches in the
+timed region), and the binary64 oracle timed on a bounded sample on the host.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("Gelem/s of H applied (procedural vs cached) & Chebyshev steps/s "
+          "at stated err")
+PEAK_FP32_TFLOPS = 157.3   # MI355X vector fp32 (published)
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def measure_apply(pm, op, X, reps, warm=2):
+    """Mean seconds per product over `reps` products (HIP events)."""
+    import torch
+    for _ in range(warm):
+        op.apply(X, Y=None)
+    Y = torch.empty_like(X)
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    op.profile(1)
+    e0.record(s)
+    for _ in range(reps):
+        op.apply(X, Y)
+    e1.record(s)
+    torch.cuda.synchronize()
+    prof = op.profile_read()
+    op.profile(0)
+    return e0.elapsed_time(e1) / 1e3 / reps, prof
+
+
+def cpu_baseline_dvr(D, budget_s=12.0):
+    """Binary64 oracle (row-by-row product) on a bounded sample of rows."""
+    import numpy as np
+    import oracle
+    from paper_2606_31598_amd import workloads
+    d = oracle.DVR(D)
+    X = workloads.wavepacket(D)
+    rows = 64
+    elapsed = 0.0
+    while True:
+        idx = np.arange(rows, dtype=np.int64) * (D // rows)
+        t0 = time.perf_counter()
+        d.apply_rows(X, idx)
+        elapsed = time.perf_counter() - t0
+        if elapsed > budget_s / 4 or rows >= D:
+            break
+        rows = min(D, rows * 4)
+    gelem = rows * D / elapsed / 1e9
+    return {"value": gelem, "unit": "Gelem/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"binary64 row-by-row sinc-DVR product, {rows} of {D} rows "
+                      f"x {D} columns, 1 vector ({elapsed:.2f} s)"}
+
+
+def stated_error_dvr(psi_host, D, t):
+    """rel-L2 of the propagated state against the exact coherent state."""
+    import numpy as np
+    import oracle
+    from oracle import chebyshev as ch
+    d = oracle.DVR(D)
+    ref = ch.coherent_state(d.x, t, 3.0, d.dx)
+    return float(np.linalg.norm(psi_host[0] - ref) / np.linalg.norm(ref))
+
+
+def run_dvr(args):
+    import numpy as np
+    import torch
+    from paper_2606_31598_amd import procmv as pm
+    from paper_2606_31598_amd import workloads
+
+    D, dt, b = args.D, 0.05, args.block
+    strat = {"procedural": pm.PROCEDURAL, "partial": pm.PARTIAL,
+             "full": pm.FULL}[args.strategy]
+    frac = {"procedural": 0.0, "partial": 0.5, "full": 1.0}[args.strategy]
+    log(f"DVR D={D} b={b} strategy={args.strategy}")
+    op = pm.Operator.dvr(D).plan(b, strat, frac)
+    c, R = op.spectral_bounds()
+    K = pm.cheb_order(R * dt, 1e-10)
+    log(f"c={c:.6g} R={R:.6g} K={K} (H products per step)")
+    psi = torch.from_numpy(workloads.wavepacket(D).astype(np.complex64)).cuda()
+    s = torch.cuda.current_stream()
+    for w in range(args.warmup):
+        op.propagate(psi, dt, nsteps=1, K=K, c=c, R=R)
+        torch.cuda.synchronize()
+        log(f"warmup step {w + 1}/{args.warmup} done")
+    op.profile(args.profile_every)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(s)
+    for k in range(args.steps):
+        op.propagate(psi, dt, nsteps=1, K=K, c=c, R=R)
+        if args.steps > 1:
+            log(f"timed step {k + 1}/{args.steps} enqueued")
+    e1.record(s)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = op.profile_read()
+    op.profile(0)
+    wall = t1 - t0
+    ev = e0.elapsed_time(e1) / 1e3
+    log(f"timed {args.steps} steps: wall {wall:.3f} s, events {ev:.3f} s")
+    elems = float(args.steps) * K * D * D
+    value = elems / wall / 1e9
+    psi_host = psi.cpu().numpy()
+    t_total = (args.warmup + args.steps) * dt
+
+    tile_avg = prof["tile_ms"] / max(prof["tile_n"], 1) / 1e3
+    red_avg = prof["reduce_ms"] / max(prof["reduce_n"], 1) / 1e3
+    flops = 4.0 * D * D      # real entry x complex vector: 2 FMA per element
+    achieved = flops / tile_avg / 1e12
+    out = {
+        "metric": METRIC, "value": value, "unit": "Gelem/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"sinc-DVR harmonic oscillator D={D}, x in [-20,20], "
+                               f"wavepacket x0=3 sigma=1, Chebyshev dt={dt}, "
+                               f"K={K} products per step, {args.strategy} b={b}",
+                   "D": D, "nvec": 1, "K": K, "dt": dt, "block_size": b,
+                   "strategy": args.strategy},
+        "cheb_steps_per_s": args.steps / wall,
+        "h_products_per_s": args.steps * K / wall,
+        "tile_kernel_avg_us": tile_avg * 1e6,
+        "reduce_kernel_avg_us": red_avg * 1e6,
+        "timed_launches": {"tile": prof["tile_n"], "reduce": prof["reduce_n"],
+                           "sampled_every": args.profile_every},
+        "roofline": {"bound": "alu", "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
+    }
+
+    if args.modes:
+        X = torch.from_numpy(workloads.gaussian_vectors(D, 1, seed=2)
+                             .astype(np.complex64)).cuda()
+        modes = {}
+        for name, st, f in [("procedural", pm.PROCEDURAL, 0.0),
+                            ("partial50", pm.PARTIAL, 0.5),
+                            ("full", pm.FULL, 1.0)]:
+            o2 = pm.Operator.dvr(D).plan(b, st, f)
+            t, pr = measure_apply(pm, o2, X, args.mode_reps)
+            info = o2.plan_info()
+            ta = pr["tile_ms"] / max(pr["tile_n"], 1) / 1e3
+            modes[name] = {"gelem_s": D * D / t / 1e9, "us_per_product": t * 1e6,
+                           "tile_us": ta * 1e6,
+                           "cache_gb": info["cache_bytes"] / 1e9,
+                           "cache_read_gb_s": info["cache_bytes"] / ta / 1e9}
+            log(f"mode {name}: {modes[name]['gelem_s']:.1f} Gelem/s")
+            o2.close()
+            torch.cuda.synchronize()
+        out["modes"] = modes
+
+    if args.cpu:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline_dvr(D)
+        out["err_vs_exact"] = stated_error_dvr(psi_host, D, t_total)
+        out["err_time"] = t_total
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--D", type=int, default=32768)
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--strategy", default="procedural",
+                    choices=["procedural", "partial", "full"])
+    ap.add_argument("--profile-every", type=int, default=16)
+    ap.add_argument("--mode-reps", type=int, default=50)
+    ap.add_argument("--no-modes", dest="modes", action="store_false")
+    ap.add_argument("--no-cpu", dest="cpu", action="store_false")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    out = run_dvr(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

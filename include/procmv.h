@@ -154,6 +154,19 @@ typedef struct {
 } procmv_plan_info_t;
 procmv_status procmv_plan_info(procmv_op_t H, procmv_plan_info_t* info);
 
+/* Measurement hook (paper Sec. IV-C: measured time per product, timed
+ * with device-side events).  With every > 0, the library records a pair of
+ * HIP events on the launch stream around every `every`-th launch of the
+ * block-product (tile) kernel and of the partial-reduction kernel issued
+ * through this handle; every <= 0 switches recording off and clears the
+ * record.  procmv_profile_read synchronises the recorded events and returns
+ * the summed durations (ms) and the number of timed launches of each kernel,
+ * then clears the record. */
+procmv_status procmv_profile_enable(procmv_op_t H, int32_t every);
+procmv_status procmv_profile_read(procmv_op_t H, double* tile_ms,
+                                  int64_t* tile_launches, double* reduce_ms,
+                                  int64_t* reduce_launches);
+
 /* Release the operator and every device buffer it owns. NULL is ignored. */
 void procmv_destroy(procmv_op_t H);
 

@@ -58,6 +58,7 @@ struct procmv_op {
     // sinc-DVR: device tables and binary64 constants
     float* d_tk = nullptr;
     float* d_v = nullptr;
+    float* d_text = nullptr;  // symmetric symbol t(k), k in (-D, D), zero at 0
     double d_const = 0.0;   // constant diagonal paired with the binary32 tables
     double dx = 0.0, vmax = 0.0;
     // plan
@@ -81,6 +82,11 @@ struct procmv_op {
     size_t acc_bytes = 0;
     double* d_norm = nullptr;
     size_t norm_bytes = 0;
+    // measurement: event pairs around sampled launches
+    int32_t prof_every = 0;
+    int64_t prof_count[2] = {0, 0};
+    std::vector<hipEvent_t> prof_ev[2];   // start, stop interleaved
+    size_t prof_used[2] = {0, 0};
 
     size_t slot_elem() const { return gen == 0 ? sizeof(float2) : sizeof(float); }
 
@@ -116,10 +122,36 @@ struct procmv_op {
         release_plan();
         dfree(d_tk);
         dfree(d_v);
+        dfree(d_text);
         dfree(d_P);
         dfree(d_q);
         dfree(d_acc);
         dfree(d_norm);
+        for (int k = 0; k < 2; ++k)
+            for (hipEvent_t e : prof_ev[k]) (void)hipEventDestroy(e);
+    }
+
+    // Event pair for launch number prof_count[kind] if it is sampled.
+    bool prof_pair(int kind, hipEvent_t& a, hipEvent_t& b)
+    {
+        if (prof_every <= 0) return false;
+        const int64_t n = prof_count[kind]++;
+        if (n % prof_every != 0) return false;
+        std::vector<hipEvent_t>& ev = prof_ev[kind];
+        if (prof_used[kind] + 2 > ev.size()) {
+            hipEvent_t e0, e1;
+            if (hipEventCreate(&e0) != hipSuccess) return false;
+            if (hipEventCreate(&e1) != hipSuccess) {
+                (void)hipEventDestroy(e0);
+                return false;
+            }
+            ev.push_back(e0);
+            ev.push_back(e1);
+        }
+        a = ev[prof_used[kind]];
+        b = ev[prof_used[kind] + 1];
+        prof_used[kind] += 2;
+        return true;
     }
 };
 
@@ -205,6 +237,11 @@ procmv_status upload_dvr(procmv_op* op)
     op->d_const = op->dvr.compensate ? d0 - 2.0 * err : d0;
     op->dx = dx;
     op->vmax = vmax;
+    std::vector<float> text(2 * D - 1, 0.f);
+    for (int64_t k = 1; k < D; ++k) text[D - 1 + k] = text[D - 1 - k] = tk[k];
+    HIP_TRY(hipMalloc((void**)&op->d_text, (2 * D - 1) * sizeof(float)));
+    HIP_TRY(hipMemcpy(op->d_text, text.data(), (2 * D - 1) * sizeof(float),
+                      hipMemcpyHostToDevice));
     HIP_TRY(hipMalloc((void**)&op->d_tk, D * sizeof(float)));
     HIP_TRY(hipMalloc((void**)&op->d_v, D * sizeof(float)));
     HIP_TRY(hipMemcpy(op->d_tk, tk.data(), D * sizeof(float), hipMemcpyHostToDevice));
@@ -212,33 +249,73 @@ procmv_status upload_dvr(procmv_op* op)
     return PROCMV_OK;
 }
 
-// Tile product of nv (1, 2, 4 or 8) vectors into the partial buffer.
+// What the reduction of a tile product must add up.
+struct TileOut {
+    int32_t n_slots = 0;
+    const float* vdiag = nullptr;
+};
+
+// Block product of nv (1, 2, 4 or 8) vectors into the partial buffer: the
+// Toeplitz kernel for a procedural sinc-DVR operator, the generic two-sided
+// tile kernel otherwise.
 procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
-                        hipStream_t s)
+                        hipStream_t s, TileOut& out)
 {
     const size_t ldp = (size_t)op->D;
-    const size_t need = (size_t)(op->n_super + 1) * nv * ldp * sizeof(float2);
+    const bool toeplitz = op->gen == 1 && op->p_cache == 0;
+    const int chunk = toeplitz ? dvr_toeplitz_chunk((int32_t)op->D) : 0;
+    out.n_slots = toeplitz ? (int32_t)((op->D + std::abs(chunk) - 1) / std::abs(chunk))
+                           : op->n_super + 1;
+    out.vdiag = toeplitz ? op->d_v : nullptr;
+    const size_t need = (size_t)out.n_slots * nv * ldp * sizeof(float2);
     procmv_status st = ensure(op->d_P, op->P_bytes, need);
     if (st != PROCMV_OK) return st;
-    TileArgs a{};
-    a.src = op->source();
-    a.D = (int32_t)op->D;
-    a.n_super = op->n_super;
-    a.st_list = op->d_st;
-    a.X = X;
-    a.ldx = ldx;
-    a.P = op->d_P;
-    a.ldp = (int64_t)ldp;
-    HIP_TRY(launch_tile_apply(a, nv, (int)op->n_st, s));
+    hipEvent_t e0, e1;
+    const bool timed = op->prof_pair(0, e0, e1);
+    if (timed) HIP_TRY(hipEventRecord(e0, s));
+    if (toeplitz) {
+        DvrToeplitzArgs a{};
+        a.D = (int32_t)op->D;
+        a.text = op->d_text;
+        a.X = X;
+        a.ldx = ldx;
+        a.P = op->d_P;
+        a.ldp = (int64_t)ldp;
+        HIP_TRY(launch_dvr_toeplitz(a, nv, chunk, s));
+    } else {
+        TileArgs a{};
+        a.src = op->source();
+        a.D = (int32_t)op->D;
+        a.n_super = op->n_super;
+        a.st_list = op->d_st;
+        a.X = X;
+        a.ldx = ldx;
+        a.P = op->d_P;
+        a.ldp = (int64_t)ldp;
+        HIP_TRY(launch_tile_apply(a, nv, (int)op->n_st, s));
+    }
+    if (timed) HIP_TRY(hipEventRecord(e1, s));
     return PROCMV_OK;
 }
 
-ReduceArgs reduce_args(procmv_op* op, int nv)
+procmv_status run_reduce(procmv_op* op, const ReduceArgs& r, Epi mode,
+                         hipStream_t s)
+{
+    hipEvent_t e0, e1;
+    const bool timed = op->prof_pair(1, e0, e1);
+    if (timed) HIP_TRY(hipEventRecord(e0, s));
+    HIP_TRY(launch_reduce(r, mode, s));
+    if (timed) HIP_TRY(hipEventRecord(e1, s));
+    return PROCMV_OK;
+}
+
+ReduceArgs reduce_args(procmv_op* op, int nv, const TileOut& t)
 {
     ReduceArgs r{};
     r.D = (int32_t)op->D;
     r.nv = nv;
-    r.n_slots = op->n_super + 1;
+    r.n_slots = t.n_slots;
+    r.vdiag = t.vdiag;
     r.P = op->d_P;
     r.ldp = op->D;
     r.alpha = 1.0f;
@@ -382,7 +459,7 @@ procmv_status procmv_plan_info(procmv_op_t H, procmv_plan_info_t* info)
     info->n_pair = H->n_pair;
     info->p_cache = H->p_cache;
     info->cache_bytes = H->p_cache * (int64_t)H->b * H->b * (int64_t)H->slot_elem();
-    info->work_bytes = (int64_t)(H->n_super + 1) * 8 * H->D * (int64_t)sizeof(float2);
+    info->work_bytes = (int64_t)H->P_bytes;
     info->strategy = H->strategy;
     info->precision = H->precision;
     return PROCMV_OK;
@@ -411,16 +488,18 @@ procmv_status procmv_apply(procmv_op_t H, const void* X, int64_t ldx, void* Y,
         const int nv = chunk_nv(nvec - v0);
         const float2* Xc = (const float2*)X + (size_t)v0 * ldx;
         float2* Yc = (float2*)Y + (size_t)v0 * ldy;
-        st = run_tiles(H, Xc, ldx, nv, s);
+        TileOut to;
+        st = run_tiles(H, Xc, ldx, nv, s, to);
         if (st != PROCMV_OK) return st;
-        ReduceArgs r = reduce_args(H, nv);
+        ReduceArgs r = reduce_args(H, nv, to);
         r.X = Xc;
         r.ldx = ldx;
         r.Y = Yc;
         r.ldy = ldy;
         r.beta_hi = bhi;
         r.beta_lo = blo;
-        HIP_TRY(launch_reduce(r, Epi::kApply, s));
+        st = run_reduce(H, r, Epi::kApply, s);
+        if (st != PROCMV_OK) return st;
         v0 += nv;
     }
     return PROCMV_OK;
@@ -507,9 +586,10 @@ procmv_status procmv_chebyshev_propagate(procmv_op_t H, void* psi, int64_t ld,
             int64_t lda = ld;
             float2* qb = H->d_q;
             int64_t ldb = (int64_t)D;
-            st = run_tiles(H, qa, lda, nv, s);
+            TileOut to;
+            st = run_tiles(H, qa, lda, nv, s, to);
             if (st != PROCMV_OK) return st;
-            ReduceArgs r = reduce_args(H, nv);
+            ReduceArgs r = reduce_args(H, nv, to);
             r.X = qa;
             r.ldx = lda;
             r.Yq1 = qb;
@@ -521,16 +601,17 @@ procmv_status procmv_chebyshev_propagate(procmv_op_t H, void* psi, int64_t ld,
             r.beta_lo = blo;
             r.a0 = a[0];
             r.a1 = a[1];
-            HIP_TRY(launch_reduce(r, Epi::kChebFirst, s));
+            st = run_reduce(H, r, Epi::kChebFirst, s);
+            if (st != PROCMV_OK) return st;
             // cur = qb (q1), prev = qa (q0)
             float2* cur = qb;
             int64_t ldc = ldb;
             float2* prev = qa;
             int64_t ldpv = lda;
             for (int k = 1; k < K; ++k) {
-                st = run_tiles(H, cur, ldc, nv, s);
+                st = run_tiles(H, cur, ldc, nv, s, to);
                 if (st != PROCMV_OK) return st;
-                ReduceArgs rs = reduce_args(H, nv);
+                ReduceArgs rs = reduce_args(H, nv, to);
                 rs.X = cur;
                 rs.ldx = ldc;
                 rs.Y = prev;   // q_{k-1} in, q_{k+1} out
@@ -541,7 +622,8 @@ procmv_status procmv_chebyshev_propagate(procmv_op_t H, void* psi, int64_t ld,
                 rs.beta_hi = bhi;
                 rs.beta_lo = blo;
                 rs.a0 = a[k + 1];
-                HIP_TRY(launch_reduce(rs, Epi::kChebStep, s));
+                st = run_reduce(H, rs, Epi::kChebStep, s);
+                if (st != PROCMV_OK) return st;
                 std::swap(cur, prev);
                 std::swap(ldc, ldpv);
             }
@@ -573,6 +655,44 @@ procmv_status procmv_get_entries(procmv_op_t H, int64_t r0, int64_t c0,
     if ((int64_t)nr * nc == 0) return PROCMV_OK;
     SourceArgs src = H->source();
     HIP_TRY(launch_get_entries(src, r0, c0, nr, nc, (float2*)out_dev, (hipStream_t)stream));
+    return PROCMV_OK;
+}
+
+procmv_status procmv_profile_enable(procmv_op_t H, int32_t every)
+{
+    procmv_status st = check_op(H);
+    if (st != PROCMV_OK) return st;
+    H->prof_every = every > 0 ? every : 0;
+    for (int k = 0; k < 2; ++k) {
+        H->prof_count[k] = 0;
+        H->prof_used[k] = 0;
+    }
+    return PROCMV_OK;
+}
+
+procmv_status procmv_profile_read(procmv_op_t H, double* tile_ms,
+                                  int64_t* tile_launches, double* reduce_ms,
+                                  int64_t* reduce_launches)
+{
+    procmv_status st = check_op(H);
+    if (st != PROCMV_OK) return st;
+    double ms[2] = {0.0, 0.0};
+    int64_t n[2] = {0, 0};
+    for (int k = 0; k < 2; ++k) {
+        for (size_t q = 0; q + 1 < H->prof_used[k]; q += 2) {
+            HIP_TRY(hipEventSynchronize(H->prof_ev[k][q + 1]));
+            float t = 0.f;
+            HIP_TRY(hipEventElapsedTime(&t, H->prof_ev[k][q], H->prof_ev[k][q + 1]));
+            ms[k] += (double)t;
+            n[k] += 1;
+        }
+        H->prof_used[k] = 0;
+        H->prof_count[k] = 0;
+    }
+    if (tile_ms) *tile_ms = ms[0];
+    if (tile_launches) *tile_launches = n[0];
+    if (reduce_ms) *reduce_ms = ms[1];
+    if (reduce_launches) *reduce_launches = n[1];
     return PROCMV_OK;
 }
 

@@ -272,6 +272,11 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
         sy += q.y;
     }
     const float2 x = a.X[v * a.ldx + i];
+    if (a.vdiag != nullptr) {
+        const float vd = a.vdiag[i];
+        sx = __builtin_fmaf(vd, x.x, sx);
+        sy = __builtin_fmaf(vd, x.y, sy);
+    }
     // h = alpha * y + (beta_hi + beta_lo) * x
     const float bx = __builtin_fmaf(a.beta_hi, x.x, a.beta_lo * x.x);
     const float by = __builtin_fmaf(a.beta_hi, x.y, a.beta_lo * x.y);

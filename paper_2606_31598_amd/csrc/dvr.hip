@@ -1,0 +1,162 @@
+// Sinc-DVR product on the VALU: analytic generation (paper Sec. III) of a
+// Toeplitz-plus-diagonal operator fused with the block product.
+//
+// The off-diagonal entries depend only on k = i - j, so the block H^[n,m]
+// restricted to a row band and a column chunk is read from a window of the
+// symbol t(k) that is staged in LDS (2 * chunk - 1 values per band) and never
+// formed as a dense array.  Each lane owns RB consecutive rows; columns are
+// walked four at a time with the matching x values broadcast from scalar
+// registers, and the four new symbol values a lane needs per step are one
+// aligned 16-byte LDS read, the other RB - 1 + 3 being carried in registers
+// (a sliding window).  The zero-diagonal Toeplitz sum of each column chunk
+// goes to one partial slot; the fixed-order reduction adds the chunks, the
+// site potential v_i x_i and the constant diagonal.
+#include <cstdlib>
+
+#include "kernels.h"
+
+namespace procmv {
+
+namespace {
+
+template <int NV, int RB, int CHUNK>
+__global__ __launch_bounds__(256) void dvr_toeplitz_kernel(DvrToeplitzArgs a)
+{
+    constexpr int CS = 8;                        // columns per step
+    constexpr int BAND = 256 * RB;               // rows per workgroup
+    constexpr int NSYM = BAND + CHUNK - 1;       // symbol window of the tile
+    constexpr int NSYM4 = (NSYM + 3) / 4 + 2;
+    static_assert(RB % 4 == 0 && CHUNK % CS == 0, "tile shape");
+    __shared__ float4 sym4[NSYM4];
+    float* sym = (float*)sym4;
+
+    const int D = a.D;
+    const int band = blockIdx.x;                 // row band
+    const int chunk = blockIdx.y;                // column chunk (= partial slot)
+    const int r0 = band * BAND;
+    const int c0 = chunk * CHUNK;
+    // sym[s] = t(k), k = s + kmin, kmin = r0 - (c0 + CHUNK - 1)
+    const int kmin = r0 - (c0 + CHUNK - 1);
+    for (int s = threadIdx.x; s < 4 * NSYM4; s += 256) {
+        const int k = s + kmin;
+        float t = 0.f;
+        if (s < NSYM && k > -D && k < D) t = a.text[k + D - 1];
+        sym[s] = t;
+    }
+    __syncthreads();
+
+    const int i0 = r0 + threadIdx.x * RB;        // first row of this lane
+    float2 acc[RB][NV];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[r][v] = make_float2(0.f, 0.f);
+
+    // Window of the RB + CS - 1 symbol values t(i0 + r - (j + c)),
+    // r in [0, RB), c in [0, CS): win[e], e = r - c + CS - 1, sits at LDS
+    // position lbase - CS m + e - (CS - 1) for the step j = c0 + CS m.
+    constexpr int NW = RB + CS - 1;
+    float win[NW];
+    const int lbase = threadIdx.x * RB + CHUNK - 1;   // i0 - c0 - kmin
+#pragma unroll
+    for (int e = CS; e < NW; ++e) win[e] = sym[lbase - (CS - 1) + e];
+
+    const int ncol = min(CHUNK, D - c0);
+    const int nfull = ncol / CS;                 // steps with every column in range
+    const float2* __restrict__ xb = a.X + c0;
+    for (int m = 0; m < (ncol + CS - 1) / CS; ++m) {
+        const int pos = (lbase - CS * m - (CS - 1)) >> 2;
+#pragma unroll
+        for (int q = 0; q < CS / 4; ++q) {
+            const float4 nw = sym4[pos + q];
+            win[4 * q + 0] = nw.x;
+            win[4 * q + 1] = nw.y;
+            win[4 * q + 2] = nw.z;
+            win[4 * q + 3] = nw.w;
+        }
+        const bool full = m < nfull;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            float2 x[CS];
+            const float2* xv = xb + v * a.ldx;
+            if (full) {
+#pragma unroll
+                for (int c = 0; c < CS; ++c) x[c] = xv[CS * m + c];
+            } else {
+                // ragged last step: clamped (in-range) reads, zero past the end
+#pragma unroll
+                for (int c = 0; c < CS; ++c) {
+                    const int cc = CS * m + c;
+                    const float2 t = xv[cc < ncol ? cc : ncol - 1];
+                    x[c] = cc < ncol ? t : make_float2(0.f, 0.f);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CS; ++c)
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const float t = win[r - c + CS - 1];
+                    acc[r][v].x = __builtin_fmaf(t, x[c].x, acc[r][v].x);
+                    acc[r][v].y = __builtin_fmaf(t, x[c].y, acc[r][v].y);
+                }
+        }
+        // slide: the next step's e >= CS are this step's e - CS
+#pragma unroll
+        for (int e = NW - 1; e >= CS; --e) win[e] = win[e - CS];
+    }
+
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const int i = i0 + r;
+        if (i < D) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                a.P[((size_t)chunk * NV + v) * a.ldp + i] = acc[r][v];
+        }
+    }
+}
+
+template <int NV, int RB, int CHUNK>
+hipError_t launch_cfg(const DvrToeplitzArgs& a, hipStream_t s)
+{
+    const dim3 grid((unsigned)((a.D + 256 * RB - 1) / (256 * RB)),
+                    (unsigned)((a.D + CHUNK - 1) / CHUNK));
+    hipLaunchKernelGGL((dvr_toeplitz_kernel<NV, RB, CHUNK>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int NV>
+hipError_t launch_dvr_nv(const DvrToeplitzArgs& a, int chunk, hipStream_t s)
+{
+    switch (chunk) {
+    case 256: return launch_cfg<NV, 4, 256>(a, s);
+    case 512: return launch_cfg<NV, 8, 512>(a, s);
+    case 1024: return launch_cfg<NV, 8, 1024>(a, s);
+    case 2048: return launch_cfg<NV, 8, 2048>(a, s);
+    case -512: return launch_cfg<NV, 4, 512>(a, s);
+    case -1024: return launch_cfg<NV, 4, 1024>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int dvr_toeplitz_chunk(int32_t D)
+{
+    if (const char* e = getenv("PROCMV_DVR_CHUNK")) return atoi(e);
+    return D >= 16384 ? 1024 : 256;
+}
+
+hipError_t launch_dvr_toeplitz(const DvrToeplitzArgs& a, int nv, int chunk,
+                               hipStream_t s)
+{
+    switch (nv) {
+    case 1: return launch_dvr_nv<1>(a, chunk, s);
+    case 2: return launch_dvr_nv<2>(a, chunk, s);
+    case 4: return launch_dvr_nv<4>(a, chunk, s);
+    case 8: return launch_dvr_nv<8>(a, chunk, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace procmv

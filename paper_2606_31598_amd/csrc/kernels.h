@@ -36,6 +36,17 @@ struct TileArgs {
     int64_t ldp;
 };
 
+// Sinc-DVR Toeplitz product: row bands x column chunks, one partial slot per
+// chunk.  text[k + D - 1] = t(k) for |k| < D, zero at k = 0.
+struct DvrToeplitzArgs {
+    int32_t D;
+    const float* text;
+    const float2* X;
+    int64_t ldx;
+    float2* P;                // slot = column chunk, vector v at P + (s * nv + v) * ldp
+    int64_t ldp;
+};
+
 // Epilogue of the fixed-order partial reduction.
 enum class Epi : int {
     kApply = 0,     // Y = alpha y + beta x
@@ -51,6 +62,7 @@ struct ReduceArgs {
     int64_t ldp;
     const float2* X;          // the vectors the product was applied to
     int64_t ldx;
+    const float* vdiag;       // optional site diagonal: y += vdiag[i] x_i first
     float2* Y;                // kApply: output; kChebStep: q_prev in, q_next out
     int64_t ldy;
     float2* Yq1;              // kChebFirst: q1 out
@@ -71,6 +83,10 @@ hipError_t launch_cache_fill(const SourceArgs& src, int32_t D,
 hipError_t launch_get_entries(const SourceArgs& src, int64_t r0, int64_t c0,
                               int32_t nr, int32_t nc, float2* out,
                               hipStream_t s);
+// Sinc-DVR Toeplitz product (defined in dvr.hip).
+int dvr_toeplitz_chunk(int32_t D);
+hipError_t launch_dvr_toeplitz(const DvrToeplitzArgs& a, int nv, int chunk,
+                               hipStream_t s);
 // Chebyshev helpers (defined in cheb.hip).
 hipError_t launch_cheb_finish(int32_t D, int32_t nv, const double2* acc,
                               int64_t ldacc, double2 phase, float2* psi,

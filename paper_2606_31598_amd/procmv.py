@@ -24,7 +24,8 @@ EXPORTS = [
     "procmv_create_operator", "procmv_plan", "procmv_apply",
     "procmv_spectral_bounds", "procmv_cheb_order",
     "procmv_chebyshev_propagate", "procmv_get_entries", "procmv_plan_info",
-    "procmv_destroy", "procmv_last_error",
+    "procmv_destroy", "procmv_last_error", "procmv_profile_enable",
+    "procmv_profile_read",
 ]
 
 
@@ -77,6 +78,11 @@ def load():
     L.procmv_get_entries.argtypes = [vp, c.c_int64, c.c_int64, c.c_int32,
                                      c.c_int32, vp, vp]
     L.procmv_plan_info.argtypes = [vp, c.POINTER(PlanInfo)]
+    L.procmv_profile_enable.argtypes = [vp, c.c_int32]
+    L.procmv_profile_read.argtypes = [vp, c.POINTER(c.c_double),
+                                      c.POINTER(c.c_int64),
+                                      c.POINTER(c.c_double),
+                                      c.POINTER(c.c_int64)]
     L.procmv_destroy.argtypes = [vp]
     L.procmv_destroy.restype = None
     L.procmv_last_error.restype = c.c_char_p
@@ -192,6 +198,20 @@ class Operator:
             self._h, pp, ld, nv, float(dt), int(K), int(nsteps), float(c),
             float(R), optr, _stream(stream)))
         return out
+
+    def profile(self, every=1):
+        """Time every ``every``-th tile / reduction launch with HIP events
+        (0 switches it off)."""
+        _check(load().procmv_profile_enable(self._h, int(every)))
+
+    def profile_read(self) -> dict:
+        """Summed event durations (ms) and counts of the timed launches."""
+        tm, rm = ctypes.c_double(), ctypes.c_double()
+        tn, rn = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().procmv_profile_read(self._h, ctypes.byref(tm), ctypes.byref(tn),
+                                          ctypes.byref(rm), ctypes.byref(rn)))
+        return {"tile_ms": tm.value, "tile_n": tn.value,
+                "reduce_ms": rm.value, "reduce_n": rn.value}
 
     def entries(self, r0, c0, nr, nc, stream=None):
         """Generated binary32 entries of a window, as a complex64 CUDA tensor."""
