@@ -65,6 +65,7 @@ struct procmv_op {
     bool planned = false;
     int32_t b = 0, n_blk = 0;
     int strategy = 0, precision = 0;
+    int tile_shape = 1;       // VALU tile shape (see launch_tile_apply)
     double frac = 0.0;
     int64_t n_pair = 0, p_cache = 0;
     int32_t* d_pair_slot = nullptr;
@@ -252,22 +253,43 @@ procmv_status upload_dvr(procmv_op* op)
 // What the reduction of a tile product must add up.
 struct TileOut {
     int32_t n_slots = 0;
+    int32_t nv_stride = 0;
     const float* vdiag = nullptr;
 };
 
-// Block product of nv (1, 2, 4 or 8) vectors into the partial buffer: the
-// Toeplitz kernel for a procedural sinc-DVR operator, the generic two-sided
-// tile kernel otherwise.
+static_assert(kSuperM == kSuper, "the MFMA and VALU tile kernels share one super-tile list");
+
+// Whether a block of `remaining` vectors goes to the matrix cores: always in
+// split-bf16 precision, and in binary32 once there are enough vectors for the
+// per-tile product to be a contraction worth a GEMM.
+bool use_mfma(const procmv_op* op, int remaining)
+{
+    return op->precision == PROCMV_SPLIT_BF16 || remaining >= 8;
+}
+
+// Vectors handled by one tile launch.
+int chunk_vectors(const procmv_op* op, int remaining)
+{
+    if (use_mfma(op, remaining)) return remaining >= 16 ? 16 : remaining;
+    return remaining >= 8 ? 8 : remaining >= 4 ? 4 : remaining >= 2 ? 2 : 1;
+}
+
+// Block product of one chunk of nv vectors into the partial buffer: the
+// Toeplitz kernel for a procedural sinc-DVR operator in binary32 with few
+// vectors, the MFMA kernel for vector blocks on the matrix cores, the generic
+// two-sided VALU tile kernel otherwise.
 procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
                         hipStream_t s, TileOut& out)
 {
     const size_t ldp = (size_t)op->D;
-    const bool toeplitz = op->gen == 1 && op->p_cache == 0;
+    const bool mfma = use_mfma(op, nv);
+    const bool toeplitz = !mfma && op->gen == 1 && op->p_cache == 0;
     const int chunk = toeplitz ? dvr_toeplitz_chunk((int32_t)op->D) : 0;
     out.n_slots = toeplitz ? (int32_t)((op->D + std::abs(chunk) - 1) / std::abs(chunk))
                            : op->n_super + 1;
     out.vdiag = toeplitz ? op->d_v : nullptr;
-    const size_t need = (size_t)out.n_slots * nv * ldp * sizeof(float2);
+    out.nv_stride = mfma ? 16 : nv;
+    const size_t need = (size_t)out.n_slots * out.nv_stride * ldp * sizeof(float2);
     procmv_status st = ensure(op->d_P, op->P_bytes, need);
     if (st != PROCMV_OK) return st;
     hipEvent_t e0, e1;
@@ -287,12 +309,15 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
         a.src = op->source();
         a.D = (int32_t)op->D;
         a.n_super = op->n_super;
+        a.nv = nv;
         a.st_list = op->d_st;
         a.X = X;
         a.ldx = ldx;
         a.P = op->d_P;
         a.ldp = (int64_t)ldp;
-        HIP_TRY(launch_tile_apply(a, nv, (int)op->n_st, s));
+        if (mfma) HIP_TRY(launch_tile_mfma(a, op->precision == PROCMV_SPLIT_BF16 ? 1 : 0,
+                                           (int)op->n_st, s));
+        else HIP_TRY(launch_tile_apply(a, nv, op->tile_shape, (int)op->n_st, s));
     }
     if (timed) HIP_TRY(hipEventRecord(e1, s));
     return PROCMV_OK;
@@ -315,6 +340,7 @@ ReduceArgs reduce_args(procmv_op* op, int nv, const TileOut& t)
     r.D = (int32_t)op->D;
     r.nv = nv;
     r.n_slots = t.n_slots;
+    r.nv_stride = t.nv_stride;
     r.vdiag = t.vdiag;
     r.P = op->d_P;
     r.ldp = op->D;
@@ -322,10 +348,6 @@ ReduceArgs reduce_args(procmv_op* op, int nv, const TileOut& t)
     return r;
 }
 
-int chunk_nv(int remaining)
-{
-    return remaining >= 8 ? 8 : remaining >= 4 ? 4 : remaining >= 2 ? 2 : 1;
-}
 
 }  // namespace
 
@@ -385,8 +407,6 @@ procmv_status procmv_plan(procmv_op_t H, int32_t block_size,
         return fail(PROCMV_ERR_INVALID_ARG, "cache fraction %g outside [0, 1]", cache_fraction);
     if (precision != PROCMV_FP32 && precision != PROCMV_SPLIT_BF16)
         return fail(PROCMV_ERR_INVALID_ARG, "unknown precision %d", (int)precision);
-    if (precision == PROCMV_SPLIT_BF16)
-        return fail(PROCMV_ERR_INVALID_ARG, "split-bf16 precision is not available in this build");
     hipStream_t s = (hipStream_t)stream;
     H->release_plan();
     const int64_t D = H->D;
@@ -485,7 +505,7 @@ procmv_status procmv_apply(procmv_op_t H, const void* X, int64_t ldx, void* Y,
     float bhi = 0.f, blo = 0.f;
     if (H->gen == 1) split_f32(H->d_const, bhi, blo);
     for (int v0 = 0; v0 < nvec;) {
-        const int nv = chunk_nv(nvec - v0);
+        const int nv = chunk_vectors(H, nvec - v0);
         const float2* Xc = (const float2*)X + (size_t)v0 * ldx;
         float2* Yc = (float2*)Y + (size_t)v0 * ldy;
         TileOut to;
@@ -570,7 +590,7 @@ procmv_status procmv_chebyshev_propagate(procmv_op_t H, void* psi, int64_t ld,
     hipStream_t s = (hipStream_t)stream;
 
     for (int v0 = 0; v0 < nvec;) {
-        const int nv = chunk_nv(nvec - v0);
+        const int nv = chunk_vectors(H, nvec - v0);
         float2* P0 = (float2*)psi + (size_t)v0 * ld;
         const size_t D = (size_t)H->D;
         st = ensure(H->d_q, H->q_bytes, (size_t)nv * D * sizeof(float2));

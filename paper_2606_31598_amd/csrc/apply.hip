@@ -52,47 +52,28 @@ __device__ __forceinline__ void rfma(float2& acc, float r, float2 x)
     acc.y = __builtin_fmaf(r, x.y, acc.y);
 }
 
-// Sum over the 64 lanes of a wave of N = 32 values per lane.  Butterfly
-// reduce-scatter: after it, lanes l and l^1 both hold the wave total of value
-// index l >> 1.
-__device__ __forceinline__ float wave_reduce_scatter32(float (&v)[32])
+// Sum over the 64 lanes of a wave of N values per lane (N = 16, 32 or 64).
+// Butterfly reduce-scatter: each halving step keeps half of the values and
+// adds the partner lane's copy of them; afterwards every lane holds the wave
+// total of value index lane / (64 / N) (the lanes of one group agree).
+template <int N>
+__device__ __forceinline__ float wave_reduce_scatter(float (&v)[N])
 {
     const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        bool up = lane & 32;
-        float keep = up ? v[16 + k] : v[k];
-        float give = up ? v[k] : v[16 + k];
-        v[k] = keep + __shfl_xor(give, 32);
-    }
+    for (int half = N / 2, mask = 32; half >= 1; half /= 2, mask /= 2) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        bool up = lane & 16;
-        float keep = up ? v[8 + k] : v[k];
-        float give = up ? v[k] : v[8 + k];
-        v[k] = keep + __shfl_xor(give, 16);
+        for (int k = 0; k < half; ++k) {
+            const bool up = lane & mask;
+            const float keep = up ? v[half + k] : v[k];
+            const float give = up ? v[k] : v[half + k];
+            v[k] = keep + __shfl_xor(give, mask);
+        }
     }
+    float r = v[0];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        bool up = lane & 8;
-        float keep = up ? v[4 + k] : v[k];
-        float give = up ? v[k] : v[4 + k];
-        v[k] = keep + __shfl_xor(give, 8);
-    }
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        bool up = lane & 4;
-        float keep = up ? v[2 + k] : v[k];
-        float give = up ? v[k] : v[2 + k];
-        v[k] = keep + __shfl_xor(give, 4);
-    }
-    {
-        bool up = lane & 2;
-        float keep = up ? v[1] : v[0];
-        float give = up ? v[0] : v[1];
-        v[0] = keep + __shfl_xor(give, 2);
-    }
-    return v[0] + __shfl_xor(v[0], 1);
+    for (int mask = 32 / N; mask >= 1; mask /= 2) r += __shfl_xor(r, mask);
+    return r;
 }
 
 // Block pair slot of the tile whose first row/column are (i0, j0).
@@ -103,20 +84,20 @@ __device__ __forceinline__ int32_t tile_slot(const SourceArgs& s, int i0, int j0
     return s.pair_slot[n * s.n_blk + m];
 }
 
+// One super-tile (sr, sc) of one operator: everything the two-sided product
+// of that super-tile contributes, written to its partial slots.
 template <int NV, int RW, int GEN>
-__global__ __launch_bounds__(256) void tile_apply_kernel(TileArgs a)
+__device__ __forceinline__ void super_tile(const TileArgs& a, int sr, int sc,
+                                           float2 (*red)[64][NV])
 {
     constexpr int TR = 4 * RW;          // rows per tile
     constexpr int SR = kSuper / TR;     // row tiles per super-tile
     constexpr int SC = kSuper / 64;     // column tiles per super-tile
-    static_assert(RW * NV == 16, "register budget assumes RW * NV == 16");
-
-    __shared__ float2 red[4][64][NV];
+    constexpr int NR = 2 * RW * NV;     // direct values reduced across lanes
+    static_assert(NR == 16 || NR == 32 || NR == 64, "tile shape");
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int2 st = a.st_list[blockIdx.x];
-    const int sr = st.x, sc = st.y;
     const bool diag_st = (sr == sc);
     const int row0 = sr * kSuper, col0 = sc * kSuper;
     const int D = a.D;
@@ -208,7 +189,7 @@ __global__ __launch_bounds__(256) void tile_apply_kernel(TileArgs a)
 
         // Direct partial of this tile row: reduce over the 64 lanes (columns),
         // slot sc.  Value index (v * RW + r) * 2 + {re, im}.
-        float vals[32];
+        float vals[NR];
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -216,9 +197,10 @@ __global__ __launch_bounds__(256) void tile_apply_kernel(TileArgs a)
                 vals[(v * RW + r) * 2 + 0] = dir[r][v].x;
                 vals[(v * RW + r) * 2 + 1] = dir[r][v].y;
             }
-        const float tot = wave_reduce_scatter32(vals);
-        if ((lane & 1) == 0) {
-            const int idx = lane >> 1;
+        const float tot = wave_reduce_scatter<NR>(vals);
+        constexpr int G = 64 / NR;          // lanes holding the same total
+        if ((lane % G) == 0) {
+            const int idx = lane / G;
             const int comp = idx & 1;
             const int r = (idx >> 1) % RW;
             const int v = (idx >> 1) / RW;
@@ -255,6 +237,31 @@ __global__ __launch_bounds__(256) void tile_apply_kernel(TileArgs a)
     }
 }
 
+template <int NV, int RW, int GEN>
+__global__ __launch_bounds__(256) void tile_apply_kernel(TileArgs a)
+{
+    __shared__ float2 red[4][64][NV];
+    const int2 st = a.st_list[blockIdx.x];
+    super_tile<NV, RW, GEN>(a, st.x, st.y, red);
+}
+
+// Batched persistent form: every workgroup walks the flattened list of
+// (instance, super-tile) items with a fixed stride; items are listed in an
+// order that keeps neighbouring workgroups on comparable work.
+template <int NV, int RW, int GEN>
+__global__ __launch_bounds__(256) void tile_apply_batched_kernel(
+    const TileArgs* __restrict__ ops, const int4* __restrict__ items,
+    int64_t n_items, const float2* xbase)
+{
+    __shared__ float2 red[4][64][NV];
+    for (int64_t q = blockIdx.x; q < n_items; q += gridDim.x) {
+        const int4 it = items[q];          // (instance, sr, sc, unused)
+        TileArgs a = ops[it.x];
+        a.X = xbase + a.xoff;
+        super_tile<NV, RW, GEN>(a, it.y, it.z, red);
+    }
+}
+
 template <Epi MODE>
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
 {
@@ -265,7 +272,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
     const int i = (int)(t - (int64_t)v * a.D);
     float sx = 0.f, sy = 0.f;
     const float2* p = a.P + (size_t)v * a.ldp + i;
-    const size_t stride = (size_t)a.nv * a.ldp;
+    const size_t stride = (size_t)a.nv_stride * a.ldp;
     for (int k = 0; k < a.n_slots; ++k) {
         float2 q = p[k * stride];
         sx += q.x;
@@ -354,17 +361,53 @@ hipError_t launch_nv(const TileArgs& a, int n_st, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int NV, int RW>
+hipError_t launch_nv_batched(const BatchTileLaunch& b, hipStream_t s)
+{
+    if (b.gen == 0)
+        hipLaunchKernelGGL((tile_apply_batched_kernel<NV, RW, 0>), dim3(b.grid), dim3(256), 0,
+                           s, b.ops, b.items, b.n_items, b.xbase);
+    else
+        hipLaunchKernelGGL((tile_apply_batched_kernel<NV, RW, 1>), dim3(b.grid), dim3(256), 0,
+                           s, b.ops, b.items, b.n_items, b.xbase);
+    return hipGetLastError();
+}
+
 }  // namespace
 
-hipError_t launch_tile_apply(const TileArgs& a, int nv, int n_st, hipStream_t s)
+// Tile shapes: rows per wave RW = (8, 16, 32) / (2 NV) for shape 0, 1, 2.
+hipError_t launch_tile_apply(const TileArgs& a, int nv, int shape, int n_st, hipStream_t s)
 {
+#define PROCMV_SHAPES(NV, R0, R1, R2)                                  \
+    if (shape == 0) return launch_nv<NV, R0>(a, n_st, s);              \
+    if (shape == 1) return launch_nv<NV, R1>(a, n_st, s);              \
+    if (shape == 2) return launch_nv<NV, R2>(a, n_st, s);              \
+    return hipErrorInvalidValue;
     switch (nv) {
-    case 1: return launch_nv<1, 16>(a, n_st, s);
-    case 2: return launch_nv<2, 8>(a, n_st, s);
-    case 4: return launch_nv<4, 4>(a, n_st, s);
-    case 8: return launch_nv<8, 2>(a, n_st, s);
+    case 1: PROCMV_SHAPES(1, 8, 16, 32)
+    case 2: PROCMV_SHAPES(2, 4, 8, 16)
+    case 4: PROCMV_SHAPES(4, 2, 4, 8)
+    case 8: PROCMV_SHAPES(8, 1, 2, 4)
     default: return hipErrorInvalidValue;
     }
+#undef PROCMV_SHAPES
+}
+
+hipError_t launch_tile_apply_batched(const BatchTileLaunch& b, hipStream_t s)
+{
+#define PROCMV_SHAPES(NV, R0, R1, R2)                                  \
+    if (b.shape == 0) return launch_nv_batched<NV, R0>(b, s);          \
+    if (b.shape == 1) return launch_nv_batched<NV, R1>(b, s);          \
+    if (b.shape == 2) return launch_nv_batched<NV, R2>(b, s);          \
+    return hipErrorInvalidValue;
+    switch (b.nv) {
+    case 1: PROCMV_SHAPES(1, 8, 16, 32)
+    case 2: PROCMV_SHAPES(2, 4, 8, 16)
+    case 4: PROCMV_SHAPES(4, 2, 4, 8)
+    case 8: PROCMV_SHAPES(8, 1, 2, 4)
+    default: return hipErrorInvalidValue;
+    }
+#undef PROCMV_SHAPES
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, Epi mode, hipStream_t s)

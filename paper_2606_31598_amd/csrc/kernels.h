@@ -13,6 +13,8 @@ namespace procmv {
 // the transposed product of super-tile (k, B), slot N_s from the transposed
 // product of the diagonal super-tile (B, B).
 constexpr int kSuper = 256;
+// Super-tile edge of the MFMA multi-vector kernel (same slot scheme).
+constexpr int kSuperM = 256;
 
 // Where the entries of one tile come from.
 struct SourceArgs {
@@ -28,12 +30,23 @@ struct SourceArgs {
 struct TileArgs {
     SourceArgs src;
     int32_t D;
-    int32_t n_super;          // N_s = ceil(D / kSuper)
+    int32_t n_super;          // N_s = ceil(D / super-tile edge)
+    int32_t nv;               // vectors in this launch (MFMA kernel: <= 16)
     const int2* st_list;      // super-tile coordinates (sr, sc), sr <= sc
     const float2* X;          // nvec-chunk base, vector v at X + v * ldx
     int64_t ldx;
+    int64_t xoff;             // batched launches: X = launch base + xoff
     float2* P;                // partials: slot s, vector v at P + (s * nv + v) * ldp
     int64_t ldp;
+};
+
+// One persistent launch over the (instance, super-tile) items of a batch.
+struct BatchTileLaunch {
+    const TileArgs* ops;      // device array, one per instance
+    const int4* items;        // (instance, sr, sc, 0)
+    int64_t n_items;
+    const float2* xbase;      // packed vectors of all instances
+    int gen, nv, shape, grid;
 };
 
 // Sinc-DVR Toeplitz product: row bands x column chunks, one partial slot per
@@ -57,6 +70,7 @@ enum class Epi : int {
 struct ReduceArgs {
     int32_t D;
     int32_t nv;
+    int32_t nv_stride;        // vector stride of the partial slots (>= nv)
     int32_t n_slots;          // N_s + 1
     const float2* P;
     int64_t ldp;
@@ -74,9 +88,14 @@ struct ReduceArgs {
 };
 
 // Launchers (defined in apply.hip).
-hipError_t launch_tile_apply(const TileArgs& a, int nv, int n_st,
+hipError_t launch_tile_apply(const TileArgs& a, int nv, int shape, int n_st,
                              hipStream_t s);
+hipError_t launch_tile_apply_batched(const BatchTileLaunch& b, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, Epi mode, hipStream_t s);
+// MFMA multi-vector tile product, nv <= 16 (defined in mfma.hip);
+// precision 0 = binary32 MFMA, 1 = split bfloat16.
+hipError_t launch_tile_mfma(const TileArgs& a, int precision, int n_st,
+                            hipStream_t s);
 hipError_t launch_cache_fill(const SourceArgs& src, int32_t D,
                              const int2* pairs, int64_t n_pairs, void* slots,
                              hipStream_t s);
