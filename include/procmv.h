@@ -167,6 +167,64 @@ procmv_status procmv_profile_read(procmv_op_t H, double* tile_ms,
                                   int64_t* tile_launches, double* reduce_ms,
                                   int64_t* reduce_launches);
 
+/* Measured tile-shape tuning (paper Sec. IV-C, Algorithm 2, applied to the
+ * kernel's launch shape): times `reps` products of nvec scratch vectors for
+ * each VALU tile shape and keeps the fastest for this handle.  Allocates and
+ * frees its scratch vectors; SYNCHRONISES the stream.  *shape_out / *best_ms
+ * (host, may be NULL) receive the choice and its mean time per product. */
+procmv_status procmv_autotune(procmv_op_t H, int32_t nvec, int32_t reps,
+                              void* stream, int32_t* shape_out, double* best_ms);
+
+/* ---- Batches of independent operators (single-GPU form of the paper's
+ * parameter-parallel execution, Sec. IV-G and Eq. planner_waves: independent
+ * tasks share the device instead of waiting for waves). -------------------
+ * All operators of a batch are planned, binary32, of one generator family,
+ * and must outlive the batch.  Vectors are PACKED in one device complex64
+ * buffer: instance k holds nvec vectors of length D_k, each contiguous,
+ * starting at element off_k = sum_{l<k} nvec * D_l.  One persistent launch
+ * walks every (instance, super-tile) item; a second launch reduces all
+ * partials in a fixed order, so a batched product is bit-identical to the
+ * per-instance products with the same tile shape. */
+typedef struct procmv_batch* procmv_batch_t;
+
+/* nvec in {1, 2, 4, 8}.  Allocates the packed partial buffers. */
+procmv_status procmv_batch_create(const procmv_op_t* ops, int32_t n,
+                                  int32_t nvec, procmv_batch_t* out);
+
+/* Packed element count, number of work items and the launch configuration
+ * (tile shape 0-2, persistent grid size, item order 0 = round-robin over
+ * instances largest first, 1 = instance by instance).  Any pointer may be
+ * NULL. */
+procmv_status procmv_batch_info(procmv_batch_t B, int64_t* total,
+                                int64_t* items, int32_t* shape, int32_t* grid,
+                                int32_t* order);
+procmv_status procmv_batch_configure(procmv_batch_t B, int32_t shape,
+                                     int32_t grid, int32_t order);
+
+/* Y_k = H_k X_k for every instance (packed X, Y; no overlap).  Async. */
+procmv_status procmv_batch_apply(procmv_batch_t B, const void* X, void* Y,
+                                 void* stream);
+
+/* Autotuner of the batched launch: times `reps` batched products for every
+ * (item order, tile shape, grid = {1,2,4,8} x compute units) and keeps the
+ * fastest.  SYNCHRONISES the stream. */
+procmv_status procmv_batch_autotune(procmv_batch_t B, const void* X, void* Y,
+                                    int32_t reps, void* stream,
+                                    double* best_ms);
+
+/* nsteps Chebyshev steps (as procmv_chebyshev_propagate) of every instance
+ * with one (c, R), dt and order K for all (K <= 0: the coefficient rule,
+ * tol 1e-10).  With use_graph != 0 one step is captured once as a HIP graph
+ * (re-captured when psi, dt, K, c or R change) and replayed nsteps times.
+ * norms_out (HOST, may be NULL): n * nvec binary64 norms after the last
+ * step; SYNCHRONISES the stream when given. */
+procmv_status procmv_batch_propagate(procmv_batch_t B, void* psi, double dt,
+                                     int32_t K, int32_t nsteps, double spec_c,
+                                     double spec_R, int32_t use_graph,
+                                     double* norms_out, void* stream);
+
+void procmv_batch_destroy(procmv_batch_t B);
+
 /* Release the operator and every device buffer it owns. NULL is ignored. */
 void procmv_destroy(procmv_op_t H);
 

@@ -434,6 +434,9 @@ procmv_status procmv_plan(procmv_op_t H, int32_t block_size,
             }
         }
     H->p_cache = (int64_t)pairs.size();
+    // Default VALU tile shape (procmv_autotune refines it): wide tiles when
+    // generation dominates, narrow ones when the loop streams the cache.
+    H->tile_shape = H->p_cache > 0 ? 0 : 2;
     // super-tile list
     H->n_super = (int32_t)((D + kSuper - 1) / kSuper);
     std::vector<int2> sts;
@@ -713,6 +716,480 @@ procmv_status procmv_profile_read(procmv_op_t H, double* tile_ms,
     if (tile_launches) *tile_launches = n[0];
     if (reduce_ms) *reduce_ms = ms[1];
     if (reduce_launches) *reduce_launches = n[1];
+    return PROCMV_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// Batches of independent operators: one persistent launch per product.
+// ------------------------------------------------------------------------
+struct procmv_batch {
+    std::vector<procmv_op*> ops;
+    int n = 0, nv = 0, gen = 0;
+    std::vector<int64_t> off;
+    int64_t total = 0;
+    std::vector<TileArgs> targs;
+    std::vector<std::vector<int4>> per_inst;   // super-tile items of each instance
+    TileArgs* d_ops = nullptr;
+    int4* d_items = nullptr;
+    int64_t n_items = 0;
+    BatchReduceItem* d_ritems = nullptr;       // apply epilogue
+    BatchReduceItem* d_citems = nullptr;       // Chebyshev epilogue
+    int64_t* d_off = nullptr;
+    float2* d_P = nullptr;
+    float2* d_q = nullptr;
+    double2* d_acc = nullptr;
+    double* d_norm = nullptr;
+    int shape = 1, grid = 1024, order = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap = nullptr;     // own stream for graph capture (the caller's
+                                   // may be the legacy null stream)
+    const void* g_psi = nullptr;
+    double g_key[4] = {0, 0, 0, 0};
+    int g_K = -1;
+
+    void drop_graph()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+        g_psi = nullptr;
+        g_K = -1;
+    }
+
+    ~procmv_batch()
+    {
+        drop_graph();
+        if (cap) (void)hipStreamDestroy(cap);
+        dfree(d_ops);
+        dfree(d_items);
+        dfree(d_ritems);
+        dfree(d_citems);
+        dfree(d_off);
+        dfree(d_P);
+        dfree(d_q);
+        dfree(d_acc);
+        dfree(d_norm);
+    }
+};
+
+namespace {
+
+procmv_status batch_upload_items(procmv_batch* B)
+{
+    std::vector<int4> items;
+    items.reserve((size_t)B->n_items);
+    if (B->order == 0) {
+        // round-robin over the instances, largest first
+        std::vector<int> idx(B->n);
+        for (int k = 0; k < B->n; ++k) idx[k] = k;
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+            return B->per_inst[x].size() > B->per_inst[y].size();
+        });
+        for (size_t q = 0;; ++q) {
+            bool any = false;
+            for (int k : idx)
+                if (q < B->per_inst[k].size()) {
+                    items.push_back(B->per_inst[k][q]);
+                    any = true;
+                }
+            if (!any) break;
+        }
+    } else {
+        for (int k = 0; k < B->n; ++k)
+            items.insert(items.end(), B->per_inst[k].begin(), B->per_inst[k].end());
+    }
+    HIP_TRY(hipMemcpy(B->d_items, items.data(), items.size() * sizeof(int4),
+                      hipMemcpyHostToDevice));
+    return PROCMV_OK;
+}
+
+procmv_status batch_tiles(procmv_batch* B, const float2* xbase, hipStream_t s)
+{
+    BatchTileLaunch L{};
+    L.ops = B->d_ops;
+    L.items = B->d_items;
+    L.n_items = B->n_items;
+    L.xbase = xbase;
+    L.gen = B->gen;
+    L.nv = B->nv;
+    L.shape = B->shape;
+    L.grid = (int)std::min<int64_t>(B->grid, B->n_items);
+    L.cached = 0;
+    for (procmv_op* op : B->ops) L.cached |= (op->p_cache > 0) ? 1 : 0;
+    HIP_TRY(launch_tile_apply_batched(L, s));
+    return PROCMV_OK;
+}
+
+BatchReduceArgs batch_rargs(procmv_batch* B, const BatchReduceItem* items)
+{
+    BatchReduceArgs r{};
+    r.items = items;
+    r.off = B->d_off;
+    r.n = B->n;
+    r.nv = B->nv;
+    r.total = B->total;
+    return r;
+}
+
+procmv_status batch_enqueue_apply(procmv_batch* B, const float2* X, float2* Y, hipStream_t s)
+{
+    procmv_status st = batch_tiles(B, X, s);
+    if (st != PROCMV_OK) return st;
+    BatchReduceArgs r = batch_rargs(B, B->d_ritems);
+    r.X = X;
+    r.Y = Y;
+    HIP_TRY(launch_reduce_batched(r, Epi::kApply, s));
+    return PROCMV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+procmv_status procmv_batch_create(const procmv_op_t* ops, int32_t n, int32_t nvec,
+                                  procmv_batch_t* out)
+{
+    if (!out) return fail(PROCMV_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    if (!ops || n < 1) return fail(PROCMV_ERR_INVALID_ARG, "empty batch");
+    if (nvec != 1 && nvec != 2 && nvec != 4 && nvec != 8)
+        return fail(PROCMV_ERR_INVALID_ARG, "batch nvec must be 1, 2, 4 or 8");
+    for (int k = 0; k < n; ++k) {
+        if (!ops[k]) return fail(PROCMV_ERR_INVALID_ARG, "operator %d is null", k);
+        if (!ops[k]->planned) return fail(PROCMV_ERR_NOT_PLANNED, "operator %d has no plan", k);
+        if (ops[k]->precision != PROCMV_FP32)
+            return fail(PROCMV_ERR_INVALID_ARG, "batched products run in binary32");
+        if (ops[k]->gen != ops[0]->gen)
+            return fail(PROCMV_ERR_INVALID_ARG, "a batch holds one generator family");
+    }
+    procmv_batch* B = new procmv_batch();
+    B->n = n;
+    B->nv = nvec;
+    B->gen = ops[0]->gen;
+    B->ops.assign(ops, ops + n);
+    B->off.resize(n);
+    int64_t poff = 0;
+    std::vector<int64_t> pstart(n);
+    for (int k = 0; k < n; ++k) {
+        B->off[k] = B->total;
+        B->total += (int64_t)nvec * ops[k]->D;
+        pstart[k] = poff;
+        poff += (int64_t)(ops[k]->n_super + 1) * nvec * ops[k]->D;
+    }
+    hipError_t e = hipMalloc((void**)&B->d_P, (size_t)poff * sizeof(float2));
+    if (e != hipSuccess) {
+        delete B;
+        return fail(PROCMV_ERR_OOM, "batch partial buffer: %s", hipGetErrorString(e));
+    }
+    B->targs.resize(n);
+    B->per_inst.resize(n);
+    std::vector<BatchReduceItem> ri(n);
+    for (int k = 0; k < n; ++k) {
+        procmv_op* op = ops[k];
+        TileArgs& a = B->targs[k];
+        a = TileArgs{};
+        a.src = op->source();
+        a.D = (int32_t)op->D;
+        a.n_super = op->n_super;
+        a.nv = nvec;
+        a.ldx = op->D;
+        a.xoff = B->off[k];
+        a.P = B->d_P + pstart[k];
+        a.ldp = op->D;
+        for (int r = 0; r < op->n_super; ++r)
+            for (int c = r; c < op->n_super; ++c) B->per_inst[k].push_back(make_int4(k, r, c, 0));
+        B->n_items += (int64_t)B->per_inst[k].size();
+        ri[k] = BatchReduceItem{};
+        ri[k].D = (int32_t)op->D;
+        ri[k].n_slots = op->n_super + 1;
+        ri[k].off = B->off[k];
+        ri[k].P = a.P;
+        ri[k].ldp = op->D;
+        ri[k].alpha = 1.0f;
+        if (op->gen == 1) split_f32(op->d_const, ri[k].beta_hi, ri[k].beta_lo);
+        ri[k].phase = double2{1.0, 0.0};
+    }
+    procmv_status st = PROCMV_OK;
+#define BTRY(expr)                                                           \
+    do {                                                                     \
+        hipError_t e_ = (expr);                                              \
+        if (e_ != hipSuccess) {                                              \
+            st = fail(e_ == hipErrorOutOfMemory ? PROCMV_ERR_OOM : PROCMV_ERR_HIP, \
+                      "%s: %s", #expr, hipGetErrorString(e_));               \
+            delete B;                                                        \
+            return st;                                                       \
+        }                                                                    \
+    } while (0)
+    BTRY(hipMalloc((void**)&B->d_ops, n * sizeof(TileArgs)));
+    BTRY(hipMemcpy(B->d_ops, B->targs.data(), n * sizeof(TileArgs), hipMemcpyHostToDevice));
+    BTRY(hipMalloc((void**)&B->d_items, B->n_items * sizeof(int4)));
+    BTRY(hipMalloc((void**)&B->d_ritems, n * sizeof(BatchReduceItem)));
+    BTRY(hipMalloc((void**)&B->d_citems, n * sizeof(BatchReduceItem)));
+    BTRY(hipMemcpy(B->d_ritems, ri.data(), n * sizeof(BatchReduceItem), hipMemcpyHostToDevice));
+    BTRY(hipMalloc((void**)&B->d_off, n * sizeof(int64_t)));
+    BTRY(hipMemcpy(B->d_off, B->off.data(), n * sizeof(int64_t), hipMemcpyHostToDevice));
+#undef BTRY
+    st = batch_upload_items(B);
+    if (st != PROCMV_OK) {
+        delete B;
+        return st;
+    }
+    *out = B;
+    return PROCMV_OK;
+}
+
+void procmv_batch_destroy(procmv_batch_t B) { delete B; }
+
+procmv_status procmv_batch_info(procmv_batch_t B, int64_t* total, int64_t* items,
+                                int32_t* shape, int32_t* grid, int32_t* order)
+{
+    if (!B) return fail(PROCMV_ERR_INVALID_ARG, "null batch");
+    if (total) *total = B->total;
+    if (items) *items = B->n_items;
+    if (shape) *shape = B->shape;
+    if (grid) *grid = B->grid;
+    if (order) *order = B->order;
+    return PROCMV_OK;
+}
+
+procmv_status procmv_batch_configure(procmv_batch_t B, int32_t shape, int32_t grid,
+                                     int32_t order)
+{
+    if (!B) return fail(PROCMV_ERR_INVALID_ARG, "null batch");
+    if (shape < 0 || shape > 2 || grid < 1 || order < 0 || order > 1)
+        return fail(PROCMV_ERR_INVALID_ARG, "bad launch configuration");
+    B->shape = shape;
+    B->grid = grid;
+    if (order != B->order) {
+        B->order = order;
+        procmv_status st = batch_upload_items(B);
+        if (st != PROCMV_OK) return st;
+    }
+    B->drop_graph();
+    return PROCMV_OK;
+}
+
+procmv_status procmv_batch_apply(procmv_batch_t B, const void* X, void* Y, void* stream)
+{
+    if (!B) return fail(PROCMV_ERR_INVALID_ARG, "null batch");
+    if (!X || !Y || X == Y) return fail(PROCMV_ERR_INVALID_ARG, "bad vector pointers");
+    return batch_enqueue_apply(B, (const float2*)X, (float2*)Y, (hipStream_t)stream);
+}
+
+procmv_status procmv_batch_autotune(procmv_batch_t B, const void* X, void* Y, int32_t reps,
+                                    void* stream, double* best_ms)
+{
+    if (!B) return fail(PROCMV_ERR_INVALID_ARG, "null batch");
+    if (!X || !Y || X == Y || reps < 1) return fail(PROCMV_ERR_INVALID_ARG, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0, cus = 256;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    double best = 1e30;
+    int bs = B->shape, bg = B->grid, bo = B->order;
+    const int mults[4] = {1, 2, 4, 8};
+    procmv_status st = PROCMV_OK;
+    for (int order = 0; order < 2 && st == PROCMV_OK; ++order)
+        for (int shape = 0; shape < 3 && st == PROCMV_OK; ++shape)
+            for (int mi = 0; mi < 4 && st == PROCMV_OK; ++mi) {
+                st = procmv_batch_configure(B, shape, cus * mults[mi], order);
+                if (st != PROCMV_OK) break;
+                st = batch_enqueue_apply(B, (const float2*)X, (float2*)Y, s);   // warm-up
+                if (st != PROCMV_OK) break;
+                if (hipEventRecord(e0, s) != hipSuccess) { st = PROCMV_ERR_HIP; break; }
+                for (int r = 0; r < reps && st == PROCMV_OK; ++r)
+                    st = batch_enqueue_apply(B, (const float2*)X, (float2*)Y, s);
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    st = fail(PROCMV_ERR_HIP, "autotune timing failed");
+                    break;
+                }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                const double t = ms / reps;
+                if (t < best) {
+                    best = t;
+                    bs = shape;
+                    bg = cus * mults[mi];
+                    bo = order;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != PROCMV_OK) return st;
+    st = procmv_batch_configure(B, bs, bg, bo);
+    if (best_ms) *best_ms = best;
+    return st;
+}
+
+procmv_status procmv_batch_propagate(procmv_batch_t B, void* psi, double dt, int32_t K,
+                                     int32_t nsteps, double spec_c, double spec_R,
+                                     int32_t use_graph, double* norms_out, void* stream)
+{
+    if (!B) return fail(PROCMV_ERR_INVALID_ARG, "null batch");
+    if (!psi || nsteps < 0 || !(dt >= 0.0) || !(spec_R > 0.0))
+        return fail(PROCMV_ERR_INVALID_ARG, "bad psi/nsteps/dt/R");
+    hipStream_t s = (hipStream_t)stream;
+    const float alpha = f32_down(1.0 / spec_R);
+    const double Reff = 1.0 / (double)alpha;
+    if (K <= 0) K = procmv_cheb_order(Reff * dt, 1e-10);
+    if (K < 1) return fail(PROCMV_ERR_INVALID_ARG, "Chebyshev order could not be set");
+    procmv_status st;
+    if (!B->d_q) {
+        HIP_TRY(hipMalloc((void**)&B->d_q, (size_t)B->total * sizeof(float2)));
+        HIP_TRY(hipMalloc((void**)&B->d_acc, (size_t)B->total * sizeof(double2)));
+        HIP_TRY(hipMalloc((void**)&B->d_norm, (size_t)B->n * B->nv * sizeof(double)));
+    }
+    const std::vector<double> j = bessel_j(Reff * dt, K);
+    std::vector<double2> a(K + 1);
+    for (int k = 0; k <= K; ++k) {
+        const double m = (k == 0 ? 1.0 : 2.0) * j[k];
+        const int q = k & 3;
+        a[k] = q == 0 ? double2{m, 0.0} : q == 1 ? double2{0.0, -m}
+             : q == 2 ? double2{-m, 0.0} : double2{0.0, m};
+    }
+    const bool same = B->gexec && B->g_psi == psi && B->g_K == K && B->g_key[0] == dt &&
+                      B->g_key[1] == spec_c && B->g_key[2] == spec_R;
+    if (!same) {
+        B->drop_graph();
+        std::vector<BatchReduceItem> ci(B->n);
+        for (int k = 0; k < B->n; ++k) {
+            procmv_op* op = B->ops[k];
+            ci[k] = BatchReduceItem{};
+            ci[k].D = (int32_t)op->D;
+            ci[k].n_slots = op->n_super + 1;
+            ci[k].off = B->off[k];
+            ci[k].P = B->targs[k].P;
+            ci[k].ldp = op->D;
+            ci[k].alpha = alpha;
+            const double dconst = op->gen == 1 ? op->d_const : 0.0;
+            split_f32((double)alpha * (dconst - spec_c), ci[k].beta_hi, ci[k].beta_lo);
+            ci[k].phase = double2{std::cos(spec_c * dt), -std::sin(spec_c * dt)};
+        }
+        HIP_TRY(hipMemcpy(B->d_citems, ci.data(), B->n * sizeof(BatchReduceItem),
+                          hipMemcpyHostToDevice));
+    }
+    // One Chebyshev step over every instance.
+    auto enqueue_step = [&](hipStream_t q) -> procmv_status {
+        float2* p0 = (float2*)psi;
+        procmv_status e = batch_tiles(B, p0, q);
+        if (e != PROCMV_OK) return e;
+        BatchReduceArgs r = batch_rargs(B, B->d_citems);
+        r.X = p0;
+        r.Yq1 = B->d_q;
+        r.acc = B->d_acc;
+        r.a0 = a[0];
+        r.a1 = a[1];
+        HIP_TRY(launch_reduce_batched(r, Epi::kChebFirst, q));
+        float2* cur = B->d_q;
+        float2* prev = p0;
+        for (int k = 1; k < K; ++k) {
+            e = batch_tiles(B, cur, q);
+            if (e != PROCMV_OK) return e;
+            BatchReduceArgs rs = batch_rargs(B, B->d_citems);
+            rs.X = cur;
+            rs.Y = prev;
+            rs.acc = B->d_acc;
+            rs.a0 = a[k + 1];
+            HIP_TRY(launch_reduce_batched(rs, Epi::kChebStep, q));
+            std::swap(cur, prev);
+        }
+        HIP_TRY(launch_finish_batched(B->d_citems, B->n, B->nv, B->d_acc, p0, B->d_norm, q));
+        return PROCMV_OK;
+    };
+    if (use_graph) {
+        if (!same) {
+            if (!B->cap) HIP_TRY(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+            HIP_TRY(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+            st = enqueue_step(B->cap);
+            hipGraph_t g = nullptr;
+            hipError_t ec = hipStreamEndCapture(B->cap, &g);
+            if (st != PROCMV_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (ec != hipSuccess)
+                return fail(PROCMV_ERR_HIP, "graph capture: %s", hipGetErrorString(ec));
+            B->graph = g;
+            HIP_TRY(hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0));
+            B->g_psi = psi;
+            B->g_K = K;
+            B->g_key[0] = dt;
+            B->g_key[1] = spec_c;
+            B->g_key[2] = spec_R;
+        }
+        for (int step = 0; step < nsteps; ++step) HIP_TRY(hipGraphLaunch(B->gexec, s));
+    } else {
+        for (int step = 0; step < nsteps; ++step) {
+            st = enqueue_step(s);
+            if (st != PROCMV_OK) return st;
+        }
+    }
+    if (norms_out && nsteps > 0) {
+        std::vector<double> n2((size_t)B->n * B->nv);
+        HIP_TRY(hipMemcpyAsync(n2.data(), B->d_norm, n2.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (size_t q = 0; q < n2.size(); ++q) norms_out[q] = std::sqrt(n2[q]);
+    }
+    return PROCMV_OK;
+}
+
+procmv_status procmv_autotune(procmv_op_t H, int32_t nvec, int32_t reps, void* stream,
+                              int32_t* shape_out, double* best_ms)
+{
+    procmv_status st = check_op(H);
+    if (st != PROCMV_OK) return st;
+    if (!H->planned) return fail(PROCMV_ERR_NOT_PLANNED, "autotune before procmv_plan");
+    if (nvec < 1 || reps < 1) return fail(PROCMV_ERR_INVALID_ARG, "bad nvec/reps");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = (size_t)nvec * H->D * sizeof(float2);
+    void *X = nullptr, *Y = nullptr;
+    HIP_TRY(hipMalloc(&X, bytes));
+    if (hipMalloc(&Y, bytes) != hipSuccess) {
+        (void)hipFree(X);
+        return fail(PROCMV_ERR_OOM, "autotune scratch vectors");
+    }
+    (void)hipMemsetAsync(X, 0, bytes, s);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    double best = 1e30;
+    int bshape = H->tile_shape;
+    for (int shape = 0; shape < 3 && st == PROCMV_OK; ++shape) {
+        H->tile_shape = shape;
+        st = procmv_apply(H, X, H->D, Y, H->D, nvec, stream);
+        if (st != PROCMV_OK) break;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps && st == PROCMV_OK; ++r)
+            st = procmv_apply(H, X, H->D, Y, H->D, nvec, stream);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            st = fail(PROCMV_ERR_HIP, "autotune timing failed");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms / reps < best) {
+            best = ms / reps;
+            bshape = shape;
+        }
+    }
+    H->tile_shape = bshape;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(X);
+    (void)hipFree(Y);
+    if (st != PROCMV_OK) return st;
+    if (shape_out) *shape_out = bshape;
+    if (best_ms) *best_ms = best;
     return PROCMV_OK;
 }
 

@@ -86,9 +86,9 @@ __device__ __forceinline__ int32_t tile_slot(const SourceArgs& s, int i0, int j0
 
 // One super-tile (sr, sc) of one operator: everything the two-sided product
 // of that super-tile contributes, written to its partial slots.
-template <int NV, int RW, int GEN>
+template <int NV, int RW, int GEN, int SRC>
 __device__ __forceinline__ void super_tile(const TileArgs& a, int sr, int sc,
-                                           float2 (*red)[64][NV])
+                                           float2 (*red)[64][NV], float2 (*xs)[NV])
 {
     constexpr int TR = 4 * RW;          // rows per tile
     constexpr int SR = kSuper / TR;     // row tiles per super-tile
@@ -112,15 +112,18 @@ __device__ __forceinline__ void super_tile(const TileArgs& a, int sr, int sc,
         const int trow0 = row0 + rr * TR;   // first row of the tile (WG-uniform)
         const int ib = trow0 + w * RW;      // first row of this wave
         float2 dir[RW][NV];
-        float2 xi[RW][NV];
 #pragma unroll
         for (int r = 0; r < RW; ++r)
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                dir[r][v] = make_float2(0.f, 0.f);
-                int i = ib + r;
-                xi[r][v] = (i < D) ? a.X[v * a.ldx + i] : make_float2(0.f, 0.f);
-            }
+            for (int v = 0; v < NV; ++v) dir[r][v] = make_float2(0.f, 0.f);
+        // x of the tile rows, staged in LDS and read back as wave broadcasts
+        __syncthreads();
+        for (int q = threadIdx.x; q < TR * NV; q += 256) {
+            const int r = q / NV, v = q - (q / NV) * NV;
+            const int i = trow0 + r;
+            xs[r][v] = (i < D) ? a.X[v * a.ldx + i] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
 
 #pragma unroll
         for (int cc = 0; cc < SC; ++cc) {
@@ -135,53 +138,79 @@ __device__ __forceinline__ void super_tile(const TileArgs& a, int sr, int sc,
             for (int v = 0; v < NV; ++v)
                 xj[v] = jin ? a.X[v * a.ldx + j] : make_float2(0.f, 0.f);
 
-            const int32_t slot = tile_slot(a.src, trow0, tcol0);
-#pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                const int i = ib + r;
-                const bool ok = jin && (i < D) && (i <= j);
-                const bool upper = ok && (i < j);
+            const int32_t slot = SRC ? tile_slot(a.src, trow0, tcol0) : -1;
+            if (SRC && slot >= 0) {
+                // Cached tile: the RW row loads of this lane go out first.  A
+                // tile lies inside one b x b block, whose slot is allocated in
+                // full (rows/columns past D hold zeros): no bounds guard.
+                const int bb = a.src.b;
+                const int n0 = (trow0 / bb) * bb, m0 = (tcol0 / bb) * bb;
+                const size_t base = (size_t)slot * bb * bb + (size_t)(ib - n0) * bb + (j - m0);
+                float2 hc[RW];
                 if (GEN == 0) {
-                    float2 h;
-                    if (slot >= 0) {
-                        const float2* sp = (const float2*)a.src.slots +
-                                           (size_t)slot * a.src.b * a.src.b;
-                        const int ii = i - (trow0 / a.src.b) * a.src.b;
-                        const int jj = j - (tcol0 / a.src.b) * a.src.b;
-                        h = ok ? sp[(size_t)ii * a.src.b + jj] : make_float2(0.f, 0.f);
+                    const float2* sp = (const float2*)a.src.slots + base;
+#pragma unroll
+                    for (int r = 0; r < RW; ++r) hc[r] = sp[(size_t)r * bb];
+                } else {
+                    const float* sp = (const float*)a.src.slots + base;
+#pragma unroll
+                    for (int r = 0; r < RW; ++r) hc[r] = make_float2(sp[(size_t)r * bb], 0.f);
+                }
+#pragma unroll
+                for (int r = 0; r < RW; ++r) {
+                    const int i = ib + r;
+                    const bool ok = jin && (i < D) && (i <= j);
+                    const bool upper = ok && (i < j);
+                    if (GEN == 0) {
+                        const float2 h = ok ? hc[r] : make_float2(0.f, 0.f);
+                        const float2 ht = upper ? h : make_float2(0.f, 0.f);
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) {
+                            cfma(dir[r][v], h, xj[v]);
+                            cfma_conj(tr[cc][v], ht, xs[w * RW + r][v]);
+                        }
                     } else {
+                        const float hv = ok ? hc[r].x : 0.f;
+                        const float hvt = upper ? hv : 0.f;
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) {
+                            rfma(dir[r][v], hv, xj[v]);
+                            rfma(tr[cc][v], hvt, xs[w * RW + r][v]);
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < RW; ++r) {
+                    const int i = ib + r;
+                    const bool ok = jin && (i < D) && (i <= j);
+                    const bool upper = ok && (i < j);
+                    if (GEN == 0) {
                         const uint32_t ic = ok ? (uint32_t)i : 0u;
                         const uint32_t jc = ok ? (uint32_t)j : 1u;
                         uint32_t x0, x1;
                         philox_ij(ic, jc, a.src.gue.k0, a.src.gue.k1, x0, x1);
                         float z0, z1;
                         box_muller(x0, x1, z0, z1);
-                        h = (i == j) ? make_float2(a.src.gue.s_diag * z0, 0.f)
-                                     : make_float2(a.src.gue.s_off * z0, a.src.gue.s_off * z1);
-                    }
-                    if (!ok) h = make_float2(0.f, 0.f);
-                    const float2 ht = upper ? h : make_float2(0.f, 0.f);
+                        float2 h = (i == j) ? make_float2(a.src.gue.s_diag * z0, 0.f)
+                                            : make_float2(a.src.gue.s_off * z0, a.src.gue.s_off * z1);
+                        // keep at most two rows' generation chains in flight
+                        if (r & 1) __builtin_amdgcn_sched_barrier(0);
+                        if (!ok) h = make_float2(0.f, 0.f);
+                        const float2 ht = upper ? h : make_float2(0.f, 0.f);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        cfma(dir[r][v], h, xj[v]);
-                        cfma_conj(tr[cc][v], ht, xi[r][v]);
-                    }
-                } else {
-                    float hv;
-                    if (slot >= 0) {
-                        const float* sp = (const float*)a.src.slots +
-                                          (size_t)slot * a.src.b * a.src.b;
-                        const int ii = i - (trow0 / a.src.b) * a.src.b;
-                        const int jj = j - (tcol0 / a.src.b) * a.src.b;
-                        hv = ok ? sp[(size_t)ii * a.src.b + jj] : 0.f;
+                        for (int v = 0; v < NV; ++v) {
+                            cfma(dir[r][v], h, xj[v]);
+                            cfma_conj(tr[cc][v], ht, xs[w * RW + r][v]);
+                        }
                     } else {
-                        hv = ok ? dvr_entry(a.src.dvr, (uint32_t)i, (uint32_t)j) : 0.f;
-                    }
-                    const float hvt = upper ? hv : 0.f;
+                        const float hv = ok ? dvr_entry(a.src.dvr, (uint32_t)i, (uint32_t)j) : 0.f;
+                        const float hvt = upper ? hv : 0.f;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        rfma(dir[r][v], hv, xj[v]);
-                        rfma(tr[cc][v], hvt, xi[r][v]);
+                        for (int v = 0; v < NV; ++v) {
+                            rfma(dir[r][v], hv, xj[v]);
+                            rfma(tr[cc][v], hvt, xs[w * RW + r][v]);
+                        }
                     }
                 }
             }
@@ -237,46 +266,76 @@ __device__ __forceinline__ void super_tile(const TileArgs& a, int sr, int sc,
     }
 }
 
-template <int NV, int RW, int GEN>
+template <int NV, int RW, int GEN, int SRC>
 __global__ __launch_bounds__(256) void tile_apply_kernel(TileArgs a)
 {
     __shared__ float2 red[4][64][NV];
+    __shared__ float2 xs[4 * RW][NV];
     const int2 st = a.st_list[blockIdx.x];
-    super_tile<NV, RW, GEN>(a, st.x, st.y, red);
+    super_tile<NV, RW, GEN, SRC>(a, st.x, st.y, red, xs);
 }
 
 // Batched persistent form: every workgroup walks the flattened list of
 // (instance, super-tile) items with a fixed stride; items are listed in an
 // order that keeps neighbouring workgroups on comparable work.
-template <int NV, int RW, int GEN>
+template <int NV, int RW, int GEN, int SRC>
 __global__ __launch_bounds__(256) void tile_apply_batched_kernel(
     const TileArgs* __restrict__ ops, const int4* __restrict__ items,
     int64_t n_items, const float2* xbase)
 {
     __shared__ float2 red[4][64][NV];
+    __shared__ float2 xs[4 * RW][NV];
     for (int64_t q = blockIdx.x; q < n_items; q += gridDim.x) {
         const int4 it = items[q];          // (instance, sr, sc, unused)
         TileArgs a = ops[it.x];
         a.X = xbase + a.xoff;
-        super_tile<NV, RW, GEN>(a, it.y, it.z, red);
+        super_tile<NV, RW, GEN, SRC>(a, it.y, it.z, red, xs);
     }
 }
 
 template <Epi MODE>
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // 64 elements per workgroup, 4 groups of slots per element; the group
+    // sums are combined in a fixed order.
+    __shared__ float2 part[4][64];
+    const int g = threadIdx.x >> 6;
+    const int64_t t = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
     const int64_t total = (int64_t)a.nv * a.D;
-    if (t >= total) return;
-    const int v = (int)(t / a.D);
-    const int i = (int)(t - (int64_t)v * a.D);
+    const bool live = t < total;
+    const int v = live ? (int)(t / a.D) : 0;
+    const int i = live ? (int)(t - (int64_t)v * a.D) : 0;
     float sx = 0.f, sy = 0.f;
-    const float2* p = a.P + (size_t)v * a.ldp + i;
-    const size_t stride = (size_t)a.nv_stride * a.ldp;
-    for (int k = 0; k < a.n_slots; ++k) {
-        float2 q = p[k * stride];
-        sx += q.x;
-        sy += q.y;
+    if (live) {
+        const float2* p = a.P + (size_t)v * a.ldp + i;
+        const size_t stride = (size_t)a.nv_stride * a.ldp;
+        const int k0 = (a.n_slots * g) / 4, k1 = (a.n_slots * (g + 1)) / 4;
+        int k = k0;
+        for (; k + 4 <= k1; k += 4) {
+            const float2 q0 = p[(size_t)(k + 0) * stride];
+            const float2 q1 = p[(size_t)(k + 1) * stride];
+            const float2 q2 = p[(size_t)(k + 2) * stride];
+            const float2 q3 = p[(size_t)(k + 3) * stride];
+            sx += q0.x; sy += q0.y;
+            sx += q1.x; sy += q1.y;
+            sx += q2.x; sy += q2.y;
+            sx += q3.x; sy += q3.y;
+        }
+        for (; k < k1; ++k) {
+            const float2 q = p[(size_t)k * stride];
+            sx += q.x;
+            sy += q.y;
+        }
+    }
+    part[g][threadIdx.x & 63] = make_float2(sx, sy);
+    __syncthreads();
+    if (g != 0 || !live) return;
+    {
+        const int l = threadIdx.x & 63;
+        sx = part[0][l].x; sy = part[0][l].y;
+        sx += part[1][l].x; sy += part[1][l].y;
+        sx += part[2][l].x; sy += part[2][l].y;
+        sx += part[3][l].x; sy += part[3][l].y;
     }
     const float2 x = a.X[v * a.ldx + i];
     if (a.vdiag != nullptr) {
@@ -354,22 +413,37 @@ __global__ void get_entries_kernel(SourceArgs s, int64_t r0, int64_t c0,
 template <int NV, int RW>
 hipError_t launch_nv(const TileArgs& a, int n_st, hipStream_t s)
 {
-    if (a.src.gen == 0)
-        hipLaunchKernelGGL((tile_apply_kernel<NV, RW, 0>), dim3(n_st), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((tile_apply_kernel<NV, RW, 1>), dim3(n_st), dim3(256), 0, s, a);
+    const bool cached = a.src.pair_slot != nullptr;
+    const dim3 g(n_st), b(256);
+    if (a.src.gen == 0) {
+        if (cached) hipLaunchKernelGGL((tile_apply_kernel<NV, RW, 0, 1>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((tile_apply_kernel<NV, RW, 0, 0>), g, b, 0, s, a);
+    } else {
+        if (cached) hipLaunchKernelGGL((tile_apply_kernel<NV, RW, 1, 1>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((tile_apply_kernel<NV, RW, 1, 0>), g, b, 0, s, a);
+    }
     return hipGetLastError();
 }
 
 template <int NV, int RW>
 hipError_t launch_nv_batched(const BatchTileLaunch& b, hipStream_t s)
 {
-    if (b.gen == 0)
-        hipLaunchKernelGGL((tile_apply_batched_kernel<NV, RW, 0>), dim3(b.grid), dim3(256), 0,
-                           s, b.ops, b.items, b.n_items, b.xbase);
-    else
-        hipLaunchKernelGGL((tile_apply_batched_kernel<NV, RW, 1>), dim3(b.grid), dim3(256), 0,
-                           s, b.ops, b.items, b.n_items, b.xbase);
+    const dim3 g(b.grid), t(256);
+    if (b.gen == 0) {
+        if (b.cached)
+            hipLaunchKernelGGL((tile_apply_batched_kernel<NV, RW, 0, 1>), g, t, 0, s, b.ops,
+                               b.items, b.n_items, b.xbase);
+        else
+            hipLaunchKernelGGL((tile_apply_batched_kernel<NV, RW, 0, 0>), g, t, 0, s, b.ops,
+                               b.items, b.n_items, b.xbase);
+    } else {
+        if (b.cached)
+            hipLaunchKernelGGL((tile_apply_batched_kernel<NV, RW, 1, 1>), g, t, 0, s, b.ops,
+                               b.items, b.n_items, b.xbase);
+        else
+            hipLaunchKernelGGL((tile_apply_batched_kernel<NV, RW, 1, 0>), g, t, 0, s, b.ops,
+                               b.items, b.n_items, b.xbase);
+    }
     return hipGetLastError();
 }
 
@@ -413,7 +487,7 @@ hipError_t launch_tile_apply_batched(const BatchTileLaunch& b, hipStream_t s)
 hipError_t launch_reduce(const ReduceArgs& a, Epi mode, hipStream_t s)
 {
     const int64_t total = (int64_t)a.nv * a.D;
-    const dim3 grid((unsigned)((total + 255) / 256));
+    const dim3 grid((unsigned)((total + 63) / 64));
     switch (mode) {
     case Epi::kApply:
         hipLaunchKernelGGL(reduce_kernel<Epi::kApply>, grid, dim3(256), 0, s, a);

@@ -47,6 +47,7 @@ struct BatchTileLaunch {
     int64_t n_items;
     const float2* xbase;      // packed vectors of all instances
     int gen, nv, shape, grid;
+    int cached;               // some instance has cached block pairs
 };
 
 // Sinc-DVR Toeplitz product: row bands x column chunks, one partial slot per
@@ -87,6 +88,30 @@ struct ReduceArgs {
     double2 a0, a1;           // Chebyshev coefficients of the epilogue
 };
 
+// Batched reduction: per-instance description and the launch arguments.
+struct BatchReduceItem {
+    int32_t D;
+    int32_t n_slots;
+    int64_t off;              // packed element offset of the instance
+    const float2* P;          // its partial slots (vector stride nv)
+    int64_t ldp;
+    float alpha, beta_hi, beta_lo;
+    double2 phase;            // e^{-i c dt} of the Chebyshev step
+};
+
+struct BatchReduceArgs {
+    const BatchReduceItem* items;
+    const int64_t* off;       // [n] packed offsets (sorted)
+    int32_t n;
+    int32_t nv;
+    int64_t total;            // packed elements
+    const float2* X;
+    float2* Y;
+    float2* Yq1;
+    double2* acc;
+    double2 a0, a1;
+};
+
 // Launchers (defined in apply.hip).
 hipError_t launch_tile_apply(const TileArgs& a, int nv, int shape, int n_st,
                              hipStream_t s);
@@ -106,6 +131,11 @@ hipError_t launch_get_entries(const SourceArgs& src, int64_t r0, int64_t c0,
 int dvr_toeplitz_chunk(int32_t D);
 hipError_t launch_dvr_toeplitz(const DvrToeplitzArgs& a, int nv, int chunk,
                                hipStream_t s);
+// Batched reduction and completion (defined in batch.hip).
+hipError_t launch_reduce_batched(const BatchReduceArgs& a, Epi mode, hipStream_t s);
+hipError_t launch_finish_batched(const BatchReduceItem* items, int n, int nv,
+                                 const double2* acc, float2* psi, double* norm2,
+                                 hipStream_t s);
 // Chebyshev helpers (defined in cheb.hip).
 hipError_t launch_cheb_finish(int32_t D, int32_t nv, const double2* acc,
                               int64_t ldacc, double2 phase, float2* psi,

@@ -25,7 +25,9 @@ EXPORTS = [
     "procmv_spectral_bounds", "procmv_cheb_order",
     "procmv_chebyshev_propagate", "procmv_get_entries", "procmv_plan_info",
     "procmv_destroy", "procmv_last_error", "procmv_profile_enable",
-    "procmv_profile_read",
+    "procmv_profile_read", "procmv_autotune", "procmv_batch_create",
+    "procmv_batch_info", "procmv_batch_configure", "procmv_batch_apply",
+    "procmv_batch_autotune", "procmv_batch_propagate", "procmv_batch_destroy",
 ]
 
 
@@ -83,11 +85,28 @@ def load():
                                       c.POINTER(c.c_int64),
                                       c.POINTER(c.c_double),
                                       c.POINTER(c.c_int64)]
+    L.procmv_autotune.argtypes = [vp, c.c_int32, c.c_int32, vp,
+                                  c.POINTER(c.c_int32), c.POINTER(c.c_double)]
+    L.procmv_batch_create.argtypes = [c.POINTER(vp), c.c_int32, c.c_int32,
+                                      c.POINTER(vp)]
+    L.procmv_batch_info.argtypes = [vp, c.POINTER(c.c_int64), c.POINTER(c.c_int64),
+                                    c.POINTER(c.c_int32), c.POINTER(c.c_int32),
+                                    c.POINTER(c.c_int32)]
+    L.procmv_batch_configure.argtypes = [vp, c.c_int32, c.c_int32, c.c_int32]
+    L.procmv_batch_apply.argtypes = [vp, vp, vp, vp]
+    L.procmv_batch_autotune.argtypes = [vp, vp, vp, c.c_int32, vp,
+                                        c.POINTER(c.c_double)]
+    L.procmv_batch_propagate.argtypes = [vp, vp, c.c_double, c.c_int32,
+                                         c.c_int32, c.c_double, c.c_double,
+                                         c.c_int32, c.POINTER(c.c_double), vp]
+    L.procmv_batch_destroy.argtypes = [vp]
+    L.procmv_batch_destroy.restype = None
     L.procmv_destroy.argtypes = [vp]
     L.procmv_destroy.restype = None
     L.procmv_last_error.restype = c.c_char_p
     for name in EXPORTS:
-        if name in ("procmv_cheb_order", "procmv_destroy", "procmv_last_error"):
+        if name in ("procmv_cheb_order", "procmv_destroy", "procmv_last_error",
+                    "procmv_batch_destroy"):
             continue
         getattr(L, name).restype = c.c_int
     _lib = L
@@ -213,6 +232,14 @@ class Operator:
         return {"tile_ms": tm.value, "tile_n": tn.value,
                 "reduce_ms": rm.value, "reduce_n": rn.value}
 
+    def autotune(self, nvec=1, reps=3, stream=None):
+        """Measure the VALU tile shapes and keep the fastest; returns
+        (shape, ms per product)."""
+        sh, ms = ctypes.c_int32(), ctypes.c_double()
+        _check(load().procmv_autotune(self._h, int(nvec), int(reps), _stream(stream),
+                                      ctypes.byref(sh), ctypes.byref(ms)))
+        return sh.value, ms.value
+
     def entries(self, r0, c0, nr, nc, stream=None):
         """Generated binary32 entries of a window, as a complex64 CUDA tensor."""
         import torch
@@ -220,4 +247,71 @@ class Operator:
         _check(load().procmv_get_entries(self._h, int(r0), int(c0), int(nr),
                                          int(nc), ctypes.c_void_p(out.data_ptr()),
                                          _stream(stream)))
+        return out
+
+
+class Batch:
+    """Independent operators applied together in one persistent launch.
+
+    Vectors are packed: instance k's ``nvec`` vectors of length D_k start at
+    element ``offsets[k]`` of one complex64 buffer of ``total`` elements.
+    """
+
+    def __init__(self, ops, nvec):
+        L = load()
+        self.ops = list(ops)            # keep the operators alive
+        self.nvec = int(nvec)
+        arr = (ctypes.c_void_p * len(self.ops))(*[o._h.value for o in self.ops])
+        h = ctypes.c_void_p()
+        _check(L.procmv_batch_create(arr, len(self.ops), self.nvec, ctypes.byref(h)))
+        self._h = h
+        sizes = np.array([o.D for o in self.ops], dtype=np.int64)
+        self.offsets = np.concatenate([[0], np.cumsum(self.nvec * sizes)[:-1]])
+        self.total = int(self.nvec * sizes.sum())
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().procmv_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        t, it = ctypes.c_int64(), ctypes.c_int64()
+        sh, g, o = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load().procmv_batch_info(self._h, ctypes.byref(t), ctypes.byref(it),
+                                        ctypes.byref(sh), ctypes.byref(g), ctypes.byref(o)))
+        return {"total": t.value, "items": it.value, "shape": sh.value,
+                "grid": g.value, "order": o.value}
+
+    def configure(self, shape, grid, order):
+        _check(load().procmv_batch_configure(self._h, int(shape), int(grid), int(order)))
+
+    def _ptr(self, t):
+        import torch
+        if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous() \
+                or t.numel() != self.total:
+            raise ValueError(f"expected a contiguous complex64 CUDA tensor of {self.total} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def apply(self, X, Y, stream=None):
+        _check(load().procmv_batch_apply(self._h, self._ptr(X), self._ptr(Y), _stream(stream)))
+        return Y
+
+    def autotune(self, X, Y, reps=3, stream=None):
+        ms = ctypes.c_double()
+        _check(load().procmv_batch_autotune(self._h, self._ptr(X), self._ptr(Y), int(reps),
+                                            _stream(stream), ctypes.byref(ms)))
+        return ms.value
+
+    def propagate(self, psi, dt, nsteps, c, R, K=0, graph=True, norms=False, stream=None):
+        out = np.zeros(len(self.ops) * self.nvec) if norms else None
+        optr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if norms else None
+        _check(load().procmv_batch_propagate(self._h, self._ptr(psi), float(dt), int(K),
+                                             int(nsteps), float(c), float(R),
+                                             1 if graph else 0, optr, _stream(stream)))
         return out
