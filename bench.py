@@ -187,6 +187,28 @@ def run_dvr(args):
     return out
 
 
+def pmc_probe(args):
+    """Short fixed workload for hardware-counter runs: 20 products of the
+    benchmark operator (the dominant kernel) and 20 device copies of 256 MiB
+    (a plain copy kernel of known traffic, for scaling the counters)."""
+    import numpy as np
+    import torch
+    from paper_2606_31598_amd import procmv as pm
+    from paper_2606_31598_amd import workloads
+    D = args.D
+    op = pm.Operator.dvr(D).plan(args.block)
+    X = torch.from_numpy(workloads.gaussian_vectors(D, 1, seed=2).astype(np.complex64)).cuda()
+    Y = torch.empty_like(X)
+    for _ in range(20):
+        op.apply(X, Y)
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(20):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_probe": "done", "D": D, "copy_bytes": src.numel() * 4}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +222,8 @@ def main():
     ap.add_argument("--mode-reps", type=int, default=50)
     ap.add_argument("--no-modes", dest="modes", action="store_false")
     ap.add_argument("--no-cpu", dest="cpu", action="store_false")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="short fixed run for hardware-counter collection")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -208,6 +232,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
+    if args.pmc_probe:
+        pmc_probe(args)
+        return
     out = run_dvr(args)
     print(json.dumps(out), flush=True)
 

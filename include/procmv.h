@@ -175,6 +175,98 @@ procmv_status procmv_profile_read(procmv_op_t H, double* tile_ms,
 procmv_status procmv_autotune(procmv_op_t H, int32_t nvec, int32_t reps,
                               void* stream, int32_t* shape_out, double* best_ms);
 
+/* Measured microbenchmark of one (operator, plan) pair (paper Sec. IV-C,
+ * Eq. measured_matvec_time): creates the operator, times procmv_plan
+ * (allocation and cache fill) and the mean of `reps` products of nvec
+ * vectors after `warmup` untimed ones, then releases everything.  Times in
+ * ms (host outputs).  Returns PROCMV_ERR_OOM when the plan or the vectors do
+ * not fit.  SYNCHRONISES the stream. */
+procmv_status procmv_measure(procmv_generator gen, uint64_t seed, int64_t D,
+                             const void* gen_params, int32_t nvec,
+                             int32_t block_size, procmv_strategy strategy,
+                             double cache_fraction, procmv_precision precision,
+                             int32_t warmup, int32_t reps, void* stream,
+                             double* t_fill_ms, double* t_apply_ms);
+
+/* ---- Execution planner (paper Sec. IV). ----------------------------------
+ * Candidates: block size b in {128, ..., 4096} x storage mode {procedural,
+ * partial f = 0.25 / 0.5 / 0.75, full}; index = 5 * log2(b / 128) + mode.
+ * Memory model: cache = cached canonical pairs x b^2 x bytes per entry
+ * (Eq. planner_partial_cache over canonical pairs); workspace (Eq.
+ * planner_workspace) = partial slots + input/output vectors (+ Chebyshev
+ * vectors when reuse > 1); a plan is feasible when cache + workspace <=
+ * 0.9 x budget (Eq. planner_memory_constraint). */
+int32_t procmv_plan_candidate_count(void);
+procmv_status procmv_plan_candidate(int32_t idx, int32_t* block_size,
+                                    int32_t* strategy, double* cache_fraction);
+
+/* Surrogate features of (problem, plan) (paper Sec. IV-D, feature vector
+ * x(p); this library's 8): log2 D, log2 nvec, log2 budget[GB], log2 reuse,
+ * family (0 GUE, 1 DVR), log2 b, cached fraction (procedural 0, full 1),
+ * M_tot / budget.  x_out: 8 floats (host).  *feasible_out = memory test. */
+procmv_status procmv_plan_features(int64_t D, int32_t nvec, double budget_bytes,
+                                   int64_t reuse, int32_t family,
+                                   int32_t block_size, int32_t strategy,
+                                   double cache_fraction, float* x_out,
+                                   double* m_tot_out, int32_t* feasible_out);
+
+/* Machine constants of the analytic cost model (paper Eqs. runtime_overlap,
+ * seed_source_time, analytic_source_time: the throughput R_eff of the
+ * cost score made concrete), measured by microbenchmarks. */
+typedef struct {
+    double gen_rate[2];  /* canonical entries produced per second: GUE, DVR */
+    double dvr_rate;     /* sinc-DVR Toeplitz-kernel matrix elements per s   */
+    double cache_bw;     /* bytes per second read from the block cache        */
+    double flop_rate;    /* binary32 product flop/s (8 per complex element)   */
+    double launch_s;     /* fixed cost of one product (launches, reduction)   */
+} procmv_machine_model;
+
+/* Analytic (Algorithm 1) time of a plan: fill and per-product time (s). */
+procmv_status procmv_plan_model_time(const procmv_machine_model* mm, int64_t D,
+                                     int32_t nvec, int32_t family,
+                                     int32_t block_size, int32_t strategy,
+                                     double cache_fraction, int64_t reuse,
+                                     double* t_fill_s, double* t_apply_s);
+
+/* Choose among the memory-feasible candidates the one with the smallest
+ * score: planner 0 = analytic t_fill + reuse t_apply (Algorithm 1),
+ * planner 1 = learned exp(f(z)) (Algorithm 3, ranking by the surrogate's
+ * predicted total time).  mlp_params: procmv_mlp_param_count() floats;
+ * mlp_norm: 16 floats (feature means then deviations).  All host pointers.
+ * PROCMV_ERR_INFEASIBLE_PLAN when no candidate fits. */
+procmv_status procmv_plan_choose(int32_t planner, const procmv_machine_model* mm,
+                                 const float* mlp_params, const float* mlp_norm,
+                                 int64_t D, int32_t nvec, double budget_bytes,
+                                 int64_t reuse, int32_t family,
+                                 int32_t* best_idx, double* best_score);
+
+/* procmv_plan_choose for this operator, then procmv_plan with the choice
+ * (binary32). */
+procmv_status procmv_plan_auto(procmv_op_t H, int32_t nvec, double budget_bytes,
+                               int64_t reuse, int32_t planner,
+                               const procmv_machine_model* mm,
+                               const float* mlp_params, const float* mlp_norm,
+                               void* stream, int32_t* chosen_idx);
+
+/* Surrogate network on the GPU (hand-written kernels): 8 inputs, two hidden
+ * layers of 64 ReLU units, one output; parameters packed as W1 (8x64,
+ * row-major), b1, W2 (64x64), b2, W3 (64), b3.  z: n x 8 normalised
+ * features, t: n targets (log time), all HOST arrays; the calls copy to and
+ * from the device and synchronise. */
+int32_t procmv_mlp_param_count(void);
+/* One forward/backward pass: gradient of the mean squared error (Eq.
+ * nn_loss) with respect to every parameter, and the loss. */
+procmv_status procmv_mlp_grad(const float* params, const float* z,
+                              const float* t, int32_t n, float* grad_out,
+                              float* loss_out);
+/* `epochs` full-batch Adam steps from params_inout (updated in place);
+ * loss_hist (may be NULL): loss before each step. */
+procmv_status procmv_mlp_train(const float* z, const float* t, int32_t n,
+                               int32_t epochs, float lr, float* params_inout,
+                               float* loss_hist);
+procmv_status procmv_mlp_predict(const float* params, const float* z,
+                                 int32_t n, float* y_out);
+
 /* ---- Batches of independent operators (single-GPU form of the paper's
  * parameter-parallel execution, Sec. IV-G and Eq. planner_waves: independent
  * tasks share the device instead of waiting for waves). -------------------

@@ -284,9 +284,9 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
     const size_t ldp = (size_t)op->D;
     const bool mfma = use_mfma(op, nv);
     const bool toeplitz = !mfma && op->gen == 1 && op->p_cache == 0;
-    const int chunk = toeplitz ? dvr_toeplitz_chunk((int32_t)op->D) : 0;
-    out.n_slots = toeplitz ? (int32_t)((op->D + std::abs(chunk) - 1) / std::abs(chunk))
-                           : op->n_super + 1;
+    const int variant = toeplitz ? dvr_toeplitz_variant((int32_t)op->D) : 0;
+    const int chunk = toeplitz ? dvr_toeplitz_chunk_of(variant) : 1;
+    out.n_slots = toeplitz ? (int32_t)((op->D + chunk - 1) / chunk) : op->n_super + 1;
     out.vdiag = toeplitz ? op->d_v : nullptr;
     out.nv_stride = mfma ? 16 : nv;
     const size_t need = (size_t)out.n_slots * out.nv_stride * ldp * sizeof(float2);
@@ -303,7 +303,7 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
         a.ldx = ldx;
         a.P = op->d_P;
         a.ldp = (int64_t)ldp;
-        HIP_TRY(launch_dvr_toeplitz(a, nv, chunk, s));
+        HIP_TRY(launch_dvr_toeplitz(a, nv, variant, s));
     } else {
         TileArgs a{};
         a.src = op->source();
@@ -1194,3 +1194,359 @@ procmv_status procmv_autotune(procmv_op_t H, int32_t nvec, int32_t reps, void* s
 }
 
 }  // extern "C"
+
+extern "C" {
+
+procmv_status procmv_measure(procmv_generator gen, uint64_t seed, int64_t D,
+                             const void* gen_params, int32_t nvec, int32_t block_size,
+                             procmv_strategy strategy, double cache_fraction,
+                             procmv_precision precision, int32_t warmup, int32_t reps,
+                             void* stream, double* t_fill_ms, double* t_apply_ms)
+{
+    if (nvec < 1 || warmup < 0 || reps < 1)
+        return fail(PROCMV_ERR_INVALID_ARG, "bad nvec/warmup/reps");
+    hipStream_t s = (hipStream_t)stream;
+    procmv_op_t H = nullptr;
+    procmv_status st = procmv_create_operator(gen, seed, D, gen_params, &H);
+    if (st != PROCMV_OK) return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    void *X = nullptr, *Y = nullptr;
+    const size_t bytes = (size_t)nvec * D * sizeof(float2);
+    float ms = 0.f;
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (X) (void)hipFree(X);
+        if (Y) (void)hipFree(Y);
+        procmv_destroy(H);
+    };
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(PROCMV_ERR_HIP, "event creation failed");
+    }
+    // fill time: the plan call (allocation + cache fill, synchronised)
+    if (hipEventRecord(e0, s) != hipSuccess) { cleanup(); return fail(PROCMV_ERR_HIP, "event"); }
+    st = procmv_plan(H, block_size, strategy, cache_fraction, precision, stream);
+    if (st != PROCMV_OK) { cleanup(); return st; }
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (t_fill_ms) *t_fill_ms = ms;
+    if (hipMalloc(&X, bytes) != hipSuccess || hipMalloc(&Y, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(PROCMV_ERR_OOM, "vectors do not fit");
+    }
+    (void)hipMemsetAsync(X, 0, bytes, s);
+    for (int r = 0; r < warmup; ++r) {
+        st = procmv_apply(H, X, D, Y, D, nvec, stream);
+        if (st != PROCMV_OK) { cleanup(); return st; }
+    }
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r) {
+        st = procmv_apply(H, X, D, Y, D, nvec, stream);
+        if (st != PROCMV_OK) { cleanup(); return st; }
+    }
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) { cleanup(); return fail(PROCMV_ERR_HIP, "sync"); }
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (t_apply_ms) *t_apply_ms = (double)ms / reps;
+    cleanup();
+    return PROCMV_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// Planner surrogate: training and inference on the GPU.
+// ------------------------------------------------------------------------
+namespace {
+
+struct MlpWork {
+    float *p = nullptr, *z = nullptr, *t = nullptr, *y = nullptr, *a1 = nullptr, *a2 = nullptr;
+    float *gy = nullptr, *ga1 = nullptr, *ga2 = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    float* loss = nullptr;
+    ~MlpWork()
+    {
+        for (float* q : {p, z, t, y, a1, a2, gy, ga1, ga2, g, m, v, loss}) if (q) (void)hipFree(q);
+    }
+};
+
+procmv_status mlp_setup(MlpWork& w, const float* params, const float* z, const float* t, int n)
+{
+    const size_t P = kMlpParams * sizeof(float), N = (size_t)n * sizeof(float);
+    const size_t H = (size_t)n * kMlpHidden * sizeof(float);
+    HIP_TRY(hipMalloc((void**)&w.p, P));
+    HIP_TRY(hipMalloc((void**)&w.g, P));
+    HIP_TRY(hipMalloc((void**)&w.m, P));
+    HIP_TRY(hipMalloc((void**)&w.v, P));
+    HIP_TRY(hipMalloc((void**)&w.z, N * kMlpIn));
+    HIP_TRY(hipMalloc((void**)&w.t, N));
+    HIP_TRY(hipMalloc((void**)&w.y, N));
+    HIP_TRY(hipMalloc((void**)&w.gy, N));
+    HIP_TRY(hipMalloc((void**)&w.a1, H));
+    HIP_TRY(hipMalloc((void**)&w.a2, H));
+    HIP_TRY(hipMalloc((void**)&w.ga1, H));
+    HIP_TRY(hipMalloc((void**)&w.ga2, H));
+    HIP_TRY(hipMalloc((void**)&w.loss, sizeof(float)));
+    HIP_TRY(hipMemcpy(w.p, params, P, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w.z, z, N * kMlpIn, hipMemcpyHostToDevice));
+    if (t) HIP_TRY(hipMemcpy(w.t, t, N, hipMemcpyHostToDevice));
+    std::vector<float> zero(kMlpParams, 0.f);
+    HIP_TRY(hipMemcpy(w.m, zero.data(), P, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w.v, zero.data(), P, hipMemcpyHostToDevice));
+    return PROCMV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t procmv_mlp_param_count(void) { return kMlpParams; }
+
+procmv_status procmv_mlp_grad(const float* params, const float* z, const float* t, int32_t n,
+                              float* grad_out, float* loss_out)
+{
+    if (!params || !z || !t || !grad_out || n < 1)
+        return fail(PROCMV_ERR_INVALID_ARG, "bad surrogate arguments");
+    MlpWork w;
+    procmv_status st = mlp_setup(w, params, z, t, n);
+    if (st != PROCMV_OK) return st;
+    HIP_TRY(launch_mlp_forward(w.p, w.z, n, w.y, w.a1, w.a2, nullptr));
+    HIP_TRY(launch_mlp_loss(w.y, w.t, n, w.loss, nullptr));
+    HIP_TRY(launch_mlp_backward(w.p, w.z, w.y, w.t, n, w.a1, w.a2, w.gy, w.ga1, w.ga2, w.g,
+                                nullptr));
+    HIP_TRY(hipMemcpy(grad_out, w.g, kMlpParams * sizeof(float), hipMemcpyDeviceToHost));
+    if (loss_out) HIP_TRY(hipMemcpy(loss_out, w.loss, sizeof(float), hipMemcpyDeviceToHost));
+    return PROCMV_OK;
+}
+
+procmv_status procmv_mlp_train(const float* z, const float* t, int32_t n, int32_t epochs,
+                               float lr, float* params_inout, float* loss_hist)
+{
+    if (!params_inout || !z || !t || n < 1 || epochs < 0 || !(lr > 0.f))
+        return fail(PROCMV_ERR_INVALID_ARG, "bad surrogate arguments");
+    MlpWork w;
+    procmv_status st = mlp_setup(w, params_inout, z, t, n);
+    if (st != PROCMV_OK) return st;
+    for (int e = 1; e <= epochs; ++e) {
+        HIP_TRY(launch_mlp_forward(w.p, w.z, n, w.y, w.a1, w.a2, nullptr));
+        if (loss_hist) {
+            HIP_TRY(launch_mlp_loss(w.y, w.t, n, w.loss, nullptr));
+            HIP_TRY(hipMemcpy(&loss_hist[e - 1], w.loss, sizeof(float), hipMemcpyDeviceToHost));
+        }
+        HIP_TRY(launch_mlp_backward(w.p, w.z, w.y, w.t, n, w.a1, w.a2, w.gy, w.ga1, w.ga2,
+                                    w.g, nullptr));
+        HIP_TRY(launch_mlp_adam(w.p, w.g, w.m, w.v, lr, e, nullptr));
+    }
+    HIP_TRY(hipMemcpy(params_inout, w.p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost));
+    return PROCMV_OK;
+}
+
+procmv_status procmv_mlp_predict(const float* params, const float* z, int32_t n, float* y_out)
+{
+    if (!params || !z || !y_out || n < 1)
+        return fail(PROCMV_ERR_INVALID_ARG, "bad surrogate arguments");
+    MlpWork w;
+    procmv_status st = mlp_setup(w, params, z, nullptr, n);
+    if (st != PROCMV_OK) return st;
+    HIP_TRY(launch_mlp_forward(w.p, w.z, n, w.y, nullptr, nullptr, nullptr));
+    HIP_TRY(hipMemcpy(y_out, w.y, (size_t)n * sizeof(float), hipMemcpyDeviceToHost));
+    return PROCMV_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// Execution planner (paper Sec. IV: Algorithm 1 analytic, Algorithm 3
+// learned, and the measured exhaustive search that judges both).
+// ------------------------------------------------------------------------
+namespace {
+
+constexpr int kPlanBlocks[6] = {128, 256, 512, 1024, 2048, 4096};
+constexpr int kPlanModes = 5;   // procedural, partial 0.25 / 0.5 / 0.75, full
+constexpr double kPlanAlpha = 0.9;
+
+void plan_candidate(int idx, int32_t& b, int32_t& strategy, double& f)
+{
+    b = kPlanBlocks[idx / kPlanModes];
+    const int m = idx % kPlanModes;
+    strategy = m == 0 ? PROCMV_PROCEDURAL : m == 4 ? PROCMV_FULL : PROCMV_PARTIAL;
+    f = m == 0 ? 0.0 : m == 4 ? 1.0 : 0.25 * m;
+}
+
+// Memory of a plan: cache (Eq. planner_partial_cache / planner_full_cache
+// over canonical pairs) and workspace (Eq. planner_workspace: partial slots
+// plus input, output and, for repeated use, the Chebyshev vectors).
+void plan_memory(int64_t D, int32_t nvec, int family, int32_t b, int32_t strategy, double f,
+                 int64_t reuse, double& m_op, double& m_work)
+{
+    const int64_t nb = (D + b - 1) / b;
+    const int64_t npair = nb * (nb + 1) / 2;
+    int64_t p = 0;
+    if (strategy == PROCMV_FULL) p = npair;
+    else if (strategy == PROCMV_PARTIAL) p = (int64_t)std::floor(f * (double)npair);
+    const double be = family == 0 ? 8.0 : 4.0;
+    m_op = (double)p * b * b * be;
+    const int64_t ns = (D + kSuper - 1) / kSuper;
+    const int chunk = nvec >= 8 ? 16 : nvec >= 4 ? 4 : nvec >= 2 ? 2 : 1;
+    const double slots = (family == 1 && strategy == PROCMV_PROCEDURAL && nvec < 8)
+                             ? (double)((D + 511) / 512) : (double)(ns + 1);
+    m_work = slots * chunk * D * 8.0 + 2.0 * nvec * D * 8.0;
+    if (reuse > 1) m_work += (double)nvec * D * (8.0 + 16.0);
+}
+
+void plan_features(int64_t D, int32_t nvec, double budget, int64_t reuse, int family,
+                   int32_t b, int32_t strategy, double f, float* x, double* m_tot)
+{
+    double mo, mw;
+    plan_memory(D, nvec, family, b, strategy, f, reuse, mo, mw);
+    x[0] = (float)std::log2((double)D);
+    x[1] = (float)std::log2((double)nvec);
+    x[2] = (float)std::log2(budget / 1e9);
+    x[3] = (float)std::log2((double)reuse);
+    x[4] = (float)family;
+    x[5] = (float)std::log2((double)b);
+    x[6] = (float)(strategy == PROCMV_PROCEDURAL ? 0.0 : strategy == PROCMV_FULL ? 1.0 : f);
+    x[7] = (float)((mo + mw) / budget);
+    if (m_tot) *m_tot = mo + mw;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t procmv_plan_candidate_count(void)
+{
+    return (int32_t)(sizeof(kPlanBlocks) / sizeof(kPlanBlocks[0])) * kPlanModes;
+}
+
+procmv_status procmv_plan_candidate(int32_t idx, int32_t* block_size, int32_t* strategy,
+                                    double* cache_fraction)
+{
+    if (idx < 0 || idx >= procmv_plan_candidate_count() || !block_size || !strategy ||
+        !cache_fraction)
+        return fail(PROCMV_ERR_INVALID_ARG, "bad candidate index");
+    plan_candidate(idx, *block_size, *strategy, *cache_fraction);
+    return PROCMV_OK;
+}
+
+procmv_status procmv_plan_features(int64_t D, int32_t nvec, double budget_bytes, int64_t reuse,
+                                   int32_t family, int32_t block_size, int32_t strategy,
+                                   double cache_fraction, float* x_out, double* m_tot_out,
+                                   int32_t* feasible_out)
+{
+    if (D < 1 || nvec < 1 || !(budget_bytes > 0) || reuse < 1 || !x_out)
+        return fail(PROCMV_ERR_INVALID_ARG, "bad planning problem");
+    double mt = 0.0;
+    plan_features(D, nvec, budget_bytes, reuse, family, block_size, strategy, cache_fraction,
+                  x_out, &mt);
+    if (m_tot_out) *m_tot_out = mt;
+    if (feasible_out) *feasible_out = mt <= kPlanAlpha * budget_bytes ? 1 : 0;
+    return PROCMV_OK;
+}
+
+procmv_status procmv_plan_model_time(const procmv_machine_model* mm, int64_t D, int32_t nvec,
+                                     int32_t family, int32_t block_size, int32_t strategy,
+                                     double cache_fraction, int64_t reuse, double* t_fill_s,
+                                     double* t_apply_s)
+{
+    if (!mm || D < 1 || nvec < 1 || reuse < 1)
+        return fail(PROCMV_ERR_INVALID_ARG, "bad planning problem");
+    double mo, mw;
+    plan_memory(D, nvec, family, block_size, strategy, cache_fraction, reuse, mo, mw);
+    const double be = family == 0 ? 8.0 : 4.0;
+    const double cached_entries = mo / be;
+    const double canon = 0.5 * (double)D * (double)(D + 1);
+    const double gen_entries = std::max(0.0, canon - cached_entries);
+    const bool mfma = nvec >= 8;
+    const int chunks = mfma ? (nvec + 15) / 16 : (nvec + 7) / 8;
+    double t_src;
+    if (family == 1 && strategy == PROCMV_PROCEDURAL && !mfma)
+        t_src = (double)D * D * nvec / mm->dvr_rate;   // Toeplitz kernel, per vector
+    else
+        t_src = chunks * (gen_entries / mm->gen_rate[family] + mo / mm->cache_bw);
+    const double t_flop = 8.0 * (double)D * D * nvec / mm->flop_rate;
+    const double ta = mm->launch_s + std::max(t_src, t_flop);
+    const double tf = cached_entries / mm->gen_rate[family] + mo / mm->cache_bw;
+    if (t_fill_s) *t_fill_s = tf;
+    if (t_apply_s) *t_apply_s = ta;
+    return PROCMV_OK;
+}
+
+procmv_status procmv_plan_choose(int32_t planner, const procmv_machine_model* mm,
+                                 const float* mlp_params, const float* mlp_norm, int64_t D,
+                                 int32_t nvec, double budget_bytes, int64_t reuse,
+                                 int32_t family, int32_t* best_idx, double* best_score)
+{
+    const int nc = procmv_plan_candidate_count();
+    std::vector<float> feats;
+    std::vector<int> ids;
+    for (int q = 0; q < nc; ++q) {
+        int32_t b, st;
+        double f;
+        plan_candidate(q, b, st, f);
+        if (b > D && b != kPlanBlocks[0]) continue;
+        float x[kMlpIn];
+        double mt;
+        plan_features(D, nvec, budget_bytes, reuse, family, b, st, f, x, &mt);
+        if (mt > kPlanAlpha * budget_bytes) continue;   // Eq. planner_memory_constraint
+        ids.push_back(q);
+        feats.insert(feats.end(), x, x + kMlpIn);
+    }
+    if (ids.empty()) return fail(PROCMV_ERR_INFEASIBLE_PLAN, "no plan fits the memory budget");
+    std::vector<double> score(ids.size());
+    if (planner == 0) {
+        if (!mm) return fail(PROCMV_ERR_INVALID_ARG, "analytic planner needs a machine model");
+        for (size_t k = 0; k < ids.size(); ++k) {
+            int32_t b, st;
+            double f, tf, ta;
+            plan_candidate(ids[k], b, st, f);
+            procmv_status e = procmv_plan_model_time(mm, D, nvec, family, b, st, f, reuse, &tf, &ta);
+            if (e != PROCMV_OK) return e;
+            score[k] = tf + (double)reuse * ta;
+        }
+    } else if (planner == 1) {
+        if (!mlp_params || !mlp_norm)
+            return fail(PROCMV_ERR_INVALID_ARG, "learned planner needs trained parameters");
+        for (size_t k = 0; k < ids.size(); ++k)
+            for (int i = 0; i < kMlpIn; ++i) {
+                float& v = feats[k * kMlpIn + i];
+                v = (v - mlp_norm[i]) / mlp_norm[kMlpIn + i];
+            }
+        std::vector<float> y(ids.size());
+        procmv_status e = procmv_mlp_predict(mlp_params, feats.data(), (int32_t)ids.size(), y.data());
+        if (e != PROCMV_OK) return e;
+        for (size_t k = 0; k < ids.size(); ++k) score[k] = std::exp((double)y[k]);
+    } else {
+        return fail(PROCMV_ERR_INVALID_ARG, "planner must be 0 (analytic) or 1 (learned)");
+    }
+    size_t best = 0;
+    for (size_t k = 1; k < ids.size(); ++k)
+        if (score[k] < score[best]) best = k;
+    if (best_idx) *best_idx = ids[best];
+    if (best_score) *best_score = score[best];
+    return PROCMV_OK;
+}
+
+procmv_status procmv_plan_auto(procmv_op_t H, int32_t nvec, double budget_bytes,
+                               int64_t reuse, int32_t planner, const procmv_machine_model* mm,
+                               const float* mlp_params, const float* mlp_norm, void* stream,
+                               int32_t* chosen_idx)
+{
+    procmv_status st = check_op(H);
+    if (st != PROCMV_OK) return st;
+    int32_t idx = 0;
+    st = procmv_plan_choose(planner, mm, mlp_params, mlp_norm, H->D, nvec, budget_bytes, reuse,
+                            H->gen, &idx, nullptr);
+    if (st != PROCMV_OK) return st;
+    int32_t b, s;
+    double f;
+    plan_candidate(idx, b, s, f);
+    st = procmv_plan(H, b, (procmv_strategy)s, f, PROCMV_FP32, stream);
+    if (st == PROCMV_OK && chosen_idx) *chosen_idx = idx;
+    return st;
+}
+
+}  // extern "C"
+

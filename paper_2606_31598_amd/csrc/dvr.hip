@@ -3,12 +3,12 @@
 //
 // The off-diagonal entries depend only on k = i - j, so the block H^[n,m]
 // restricted to a row band and a column chunk is read from a window of the
-// symbol t(k) that is staged in LDS (2 * chunk - 1 values per band) and never
+// symbol t(k) that is staged in LDS (band + chunk - 1 values) and never
 // formed as a dense array.  Each lane owns RB consecutive rows; columns are
-// walked four at a time with the matching x values broadcast from scalar
-// registers, and the four new symbol values a lane needs per step are one
-// aligned 16-byte LDS read, the other RB - 1 + 3 being carried in registers
-// (a sliding window).  The zero-diagonal Toeplitz sum of each column chunk
+// walked CS at a time with the matching x values read as wave-wide LDS
+// broadcasts (or through the scalar cache), and the CS new symbol values a
+// lane needs per step are aligned 16-byte LDS reads, the other RB - 1 being
+// carried in registers (a sliding window).  The zero-diagonal Toeplitz sum of each column chunk
 // goes to one partial slot; the fixed-order reduction adds the chunks, the
 // site potential v_i x_i and the constant diagonal.
 #include <cstdlib>
@@ -19,15 +19,17 @@ namespace procmv {
 
 namespace {
 
-template <int NV, int RB, int CHUNK>
+template <int NV, int RB, int CHUNK, int CS, int XL>
 __global__ __launch_bounds__(256) void dvr_toeplitz_kernel(DvrToeplitzArgs a)
 {
-    constexpr int CS = 8;                        // columns per step
+    // CS columns per step; XL = 1 stages the chunk's x in LDS (broadcast
+    // reads), XL = 0 reads it through the scalar cache.
     constexpr int BAND = 256 * RB;               // rows per workgroup
     constexpr int NSYM = BAND + CHUNK - 1;       // symbol window of the tile
     constexpr int NSYM4 = (NSYM + 3) / 4 + 2;
     static_assert(RB % 4 == 0 && CHUNK % CS == 0, "tile shape");
     __shared__ float4 sym4[NSYM4];
+    __shared__ float2 xl[XL ? NV : 1][XL ? CHUNK : 1];
     float* sym = (float*)sym4;
 
     const int D = a.D;
@@ -42,6 +44,12 @@ __global__ __launch_bounds__(256) void dvr_toeplitz_kernel(DvrToeplitzArgs a)
         float t = 0.f;
         if (s < NSYM && k > -D && k < D) t = a.text[k + D - 1];
         sym[s] = t;
+    }
+    if (XL) {
+        for (int q = threadIdx.x; q < NV * CHUNK; q += 256) {
+            const int v = q / CHUNK, c = q - (q / CHUNK) * CHUNK;
+            xl[v][c] = (c0 + c < D) ? a.X[v * a.ldx + c0 + c] : make_float2(0.f, 0.f);
+        }
     }
     __syncthreads();
 
@@ -78,17 +86,22 @@ __global__ __launch_bounds__(256) void dvr_toeplitz_kernel(DvrToeplitzArgs a)
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             float2 x[CS];
-            const float2* xv = xb + v * a.ldx;
-            if (full) {
+            if (XL) {
 #pragma unroll
-                for (int c = 0; c < CS; ++c) x[c] = xv[CS * m + c];
+                for (int c = 0; c < CS; ++c) x[c] = xl[v][CS * m + c];   // zero past the end
             } else {
-                // ragged last step: clamped (in-range) reads, zero past the end
+                const float2* xv = xb + v * a.ldx;
+                if (full) {
 #pragma unroll
-                for (int c = 0; c < CS; ++c) {
-                    const int cc = CS * m + c;
-                    const float2 t = xv[cc < ncol ? cc : ncol - 1];
-                    x[c] = cc < ncol ? t : make_float2(0.f, 0.f);
+                    for (int c = 0; c < CS; ++c) x[c] = xv[CS * m + c];
+                } else {
+                    // ragged last step: clamped (in-range) reads, zero past the end
+#pragma unroll
+                    for (int c = 0; c < CS; ++c) {
+                        const int cc = CS * m + c;
+                        const float2 t = xv[cc < ncol ? cc : ncol - 1];
+                        x[c] = cc < ncol ? t : make_float2(0.f, 0.f);
+                    }
                 }
             }
 #pragma unroll
@@ -116,45 +129,58 @@ __global__ __launch_bounds__(256) void dvr_toeplitz_kernel(DvrToeplitzArgs a)
     }
 }
 
-template <int NV, int RB, int CHUNK>
+template <int NV, int RB, int CHUNK, int CS, int XL>
 hipError_t launch_cfg(const DvrToeplitzArgs& a, hipStream_t s)
 {
     const dim3 grid((unsigned)((a.D + 256 * RB - 1) / (256 * RB)),
                     (unsigned)((a.D + CHUNK - 1) / CHUNK));
-    hipLaunchKernelGGL((dvr_toeplitz_kernel<NV, RB, CHUNK>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((dvr_toeplitz_kernel<NV, RB, CHUNK, CS, XL>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
+// Variants: (rows per lane, chunk, columns per step, x in LDS).
 template <int NV>
-hipError_t launch_dvr_nv(const DvrToeplitzArgs& a, int chunk, hipStream_t s)
+hipError_t launch_dvr_nv(const DvrToeplitzArgs& a, int variant, hipStream_t s)
 {
-    switch (chunk) {
-    case 256: return launch_cfg<NV, 4, 256>(a, s);
-    case 512: return launch_cfg<NV, 8, 512>(a, s);
-    case 1024: return launch_cfg<NV, 8, 1024>(a, s);
-    case 2048: return launch_cfg<NV, 8, 2048>(a, s);
-    case -512: return launch_cfg<NV, 4, 512>(a, s);
-    case -1024: return launch_cfg<NV, 4, 1024>(a, s);
+    switch (variant) {
+    case 0: return launch_cfg<NV, 4, 256, 8, 0>(a, s);
+    case 1: return launch_cfg<NV, 4, 1024, 8, 0>(a, s);
+    case 2: return launch_cfg<NV, 4, 1024, 16, 0>(a, s);
+    case 3: return launch_cfg<NV, 4, 1024, 8, 1>(a, s);
+    case 4: return launch_cfg<NV, 8, 512, 8, 1>(a, s);
+    case 5: return launch_cfg<NV, 8, 1024, 16, 0>(a, s);
+    case 6: return launch_cfg<NV, 4, 512, 16, 1>(a, s);
+    case 7: return launch_cfg<NV, 8, 512, 16, 1>(a, s);
+    case 8: return launch_cfg<NV, 8, 256, 16, 1>(a, s);
+    case 9: return launch_cfg<NV, 4, 256, 16, 1>(a, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-int dvr_toeplitz_chunk(int32_t D)
+int dvr_toeplitz_variant(int32_t D)
 {
-    if (const char* e = getenv("PROCMV_DVR_CHUNK")) return atoi(e);
-    return D >= 16384 ? 1024 : 256;
+    if (const char* e = getenv("PROCMV_DVR_VARIANT")) return atoi(e);
+    // measured on MI355X: x staged in LDS, 4 rows per lane, 16 columns per
+    // step; 512-column chunks at large D, 256 below
+    return D >= 16384 ? 6 : 9;
 }
 
-hipError_t launch_dvr_toeplitz(const DvrToeplitzArgs& a, int nv, int chunk,
+int dvr_toeplitz_chunk_of(int variant)
+{
+    static const int chunk[10] = {256, 1024, 1024, 1024, 512, 1024, 512, 512, 256, 256};
+    return (variant >= 0 && variant < 10) ? chunk[variant] : 0;
+}
+
+hipError_t launch_dvr_toeplitz(const DvrToeplitzArgs& a, int nv, int variant,
                                hipStream_t s)
 {
     switch (nv) {
-    case 1: return launch_dvr_nv<1>(a, chunk, s);
-    case 2: return launch_dvr_nv<2>(a, chunk, s);
-    case 4: return launch_dvr_nv<4>(a, chunk, s);
-    case 8: return launch_dvr_nv<8>(a, chunk, s);
+    case 1: return launch_dvr_nv<1>(a, variant, s);
+    case 2: return launch_dvr_nv<2>(a, variant, s);
+    case 4: return launch_dvr_nv<4>(a, variant, s);
+    case 8: return launch_dvr_nv<8>(a, variant, s);
     default: return hipErrorInvalidValue;
     }
 }

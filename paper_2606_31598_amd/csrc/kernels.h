@@ -112,6 +112,12 @@ struct BatchReduceArgs {
     double2 a0, a1;
 };
 
+// Planner surrogate network: 8 inputs, two hidden layers of 64 ReLU units.
+constexpr int kMlpIn = 8;
+constexpr int kMlpHidden = 64;
+constexpr int kMlpParams = kMlpIn * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden +
+                           kMlpHidden + kMlpHidden + 1;
+
 // Launchers (defined in apply.hip).
 hipError_t launch_tile_apply(const TileArgs& a, int nv, int shape, int n_st,
                              hipStream_t s);
@@ -128,14 +134,24 @@ hipError_t launch_get_entries(const SourceArgs& src, int64_t r0, int64_t c0,
                               int32_t nr, int32_t nc, float2* out,
                               hipStream_t s);
 // Sinc-DVR Toeplitz product (defined in dvr.hip).
-int dvr_toeplitz_chunk(int32_t D);
-hipError_t launch_dvr_toeplitz(const DvrToeplitzArgs& a, int nv, int chunk,
+int dvr_toeplitz_variant(int32_t D);
+int dvr_toeplitz_chunk_of(int variant);
+hipError_t launch_dvr_toeplitz(const DvrToeplitzArgs& a, int nv, int variant,
                                hipStream_t s);
 // Batched reduction and completion (defined in batch.hip).
 hipError_t launch_reduce_batched(const BatchReduceArgs& a, Epi mode, hipStream_t s);
 hipError_t launch_finish_batched(const BatchReduceItem* items, int n, int nv,
                                  const double2* acc, float2* psi, double* norm2,
                                  hipStream_t s);
+// Surrogate network (defined in mlp.hip).
+hipError_t launch_mlp_forward(const float* p, const float* z, int n, float* y, float* a1s,
+                              float* a2s, hipStream_t s);
+hipError_t launch_mlp_backward(const float* p, const float* z, const float* y,
+                               const float* t, int n, const float* a1s, const float* a2s,
+                               float* gys, float* ga1s, float* ga2s, float* g, hipStream_t s);
+hipError_t launch_mlp_adam(float* p, const float* g, float* m, float* v, float lr, int step,
+                           hipStream_t s);
+hipError_t launch_mlp_loss(const float* y, const float* t, int n, float* loss, hipStream_t s);
 // Chebyshev helpers (defined in cheb.hip).
 hipError_t launch_cheb_finish(int32_t D, int32_t nv, const double2* acc,
                               int64_t ldacc, double2 phase, float2* psi,

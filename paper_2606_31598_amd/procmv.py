@@ -28,6 +28,10 @@ EXPORTS = [
     "procmv_profile_read", "procmv_autotune", "procmv_batch_create",
     "procmv_batch_info", "procmv_batch_configure", "procmv_batch_apply",
     "procmv_batch_autotune", "procmv_batch_propagate", "procmv_batch_destroy",
+    "procmv_measure", "procmv_plan_candidate_count", "procmv_plan_candidate",
+    "procmv_plan_features", "procmv_plan_model_time", "procmv_plan_choose",
+    "procmv_plan_auto", "procmv_mlp_param_count", "procmv_mlp_grad",
+    "procmv_mlp_train", "procmv_mlp_predict",
 ]
 
 
@@ -41,6 +45,12 @@ class DvrParams(ctypes.Structure):
     _fields_ = [("x_min", ctypes.c_double), ("x_max", ctypes.c_double),
                 ("mass", ctypes.c_double), ("omega", ctypes.c_double),
                 ("compensate", ctypes.c_int32)]
+
+
+class MachineModel(ctypes.Structure):
+    _fields_ = [("gen_rate", ctypes.c_double * 2), ("dvr_rate", ctypes.c_double),
+                ("cache_bw", ctypes.c_double), ("flop_rate", ctypes.c_double),
+                ("launch_s", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -99,6 +109,30 @@ def load():
     L.procmv_batch_propagate.argtypes = [vp, vp, c.c_double, c.c_int32,
                                          c.c_int32, c.c_double, c.c_double,
                                          c.c_int32, c.POINTER(c.c_double), vp]
+    L.procmv_measure.argtypes = [c.c_int, c.c_uint64, c.c_int64, vp, c.c_int32,
+                                 c.c_int32, c.c_int, c.c_double, c.c_int, c.c_int32,
+                                 c.c_int32, vp, c.POINTER(c.c_double),
+                                 c.POINTER(c.c_double)]
+    f32p = c.POINTER(c.c_float)
+    i32p = c.POINTER(c.c_int32)
+    f64p = c.POINTER(c.c_double)
+    L.procmv_plan_candidate_count.restype = c.c_int32
+    L.procmv_plan_candidate.argtypes = [c.c_int32, i32p, i32p, f64p]
+    L.procmv_plan_features.argtypes = [c.c_int64, c.c_int32, c.c_double, c.c_int64,
+                                       c.c_int32, c.c_int32, c.c_int32, c.c_double,
+                                       f32p, f64p, i32p]
+    L.procmv_plan_model_time.argtypes = [c.POINTER(MachineModel), c.c_int64, c.c_int32,
+                                         c.c_int32, c.c_int32, c.c_int32, c.c_double,
+                                         c.c_int64, f64p, f64p]
+    L.procmv_plan_choose.argtypes = [c.c_int32, c.POINTER(MachineModel), f32p, f32p,
+                                     c.c_int64, c.c_int32, c.c_double, c.c_int64,
+                                     c.c_int32, i32p, f64p]
+    L.procmv_plan_auto.argtypes = [vp, c.c_int32, c.c_double, c.c_int64, c.c_int32,
+                                   c.POINTER(MachineModel), f32p, f32p, vp, i32p]
+    L.procmv_mlp_param_count.restype = c.c_int32
+    L.procmv_mlp_grad.argtypes = [f32p, f32p, f32p, c.c_int32, f32p, f32p]
+    L.procmv_mlp_train.argtypes = [f32p, f32p, c.c_int32, c.c_int32, c.c_float, f32p, f32p]
+    L.procmv_mlp_predict.argtypes = [f32p, f32p, c.c_int32, f32p]
     L.procmv_batch_destroy.argtypes = [vp]
     L.procmv_batch_destroy.restype = None
     L.procmv_destroy.argtypes = [vp]
@@ -106,7 +140,8 @@ def load():
     L.procmv_last_error.restype = c.c_char_p
     for name in EXPORTS:
         if name in ("procmv_cheb_order", "procmv_destroy", "procmv_last_error",
-                    "procmv_batch_destroy"):
+                    "procmv_batch_destroy", "procmv_plan_candidate_count",
+                    "procmv_mlp_param_count"):
             continue
         getattr(L, name).restype = c.c_int
     _lib = L
@@ -138,6 +173,107 @@ def _vec_arg(t, D):
 
 def cheb_order(x: float, tol: float = 1e-10) -> int:
     return int(load().procmv_cheb_order(float(x), float(tol)))
+
+
+def _f32(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def plan_candidates():
+    """[(block_size, strategy, cache_fraction)] in candidate-index order."""
+    L = load()
+    out = []
+    for q in range(L.procmv_plan_candidate_count()):
+        b, st, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(L.procmv_plan_candidate(q, ctypes.byref(b), ctypes.byref(st), ctypes.byref(f)))
+        out.append((b.value, st.value, f.value))
+    return out
+
+
+def plan_features(D, nvec, budget_bytes, reuse, family, b, strategy, f):
+    """(8 features, M_tot bytes, feasible) of a (problem, plan) pair."""
+    x = np.zeros(8, np.float32)
+    mt, fe = ctypes.c_double(), ctypes.c_int32()
+    _check(load().procmv_plan_features(int(D), int(nvec), float(budget_bytes), int(reuse),
+                                       int(family), int(b), int(strategy), float(f),
+                                       x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                       ctypes.byref(mt), ctypes.byref(fe)))
+    return x, mt.value, bool(fe.value)
+
+
+def plan_model_time(mm, D, nvec, family, b, strategy, f, reuse):
+    tf, ta = ctypes.c_double(), ctypes.c_double()
+    _check(load().procmv_plan_model_time(ctypes.byref(mm), int(D), int(nvec), int(family),
+                                         int(b), int(strategy), float(f), int(reuse),
+                                         ctypes.byref(tf), ctypes.byref(ta)))
+    return tf.value, ta.value
+
+
+def plan_choose(planner, D, nvec, budget_bytes, reuse, family, mm=None, params=None,
+                norm=None):
+    """Index of the chosen candidate (planner 0 analytic, 1 learned)."""
+    idx, sc = ctypes.c_int32(), ctypes.c_double()
+    pa = _f32(params) if params is not None else (None, None)
+    na = _f32(norm) if norm is not None else (None, None)
+    pp, nn = pa[1], na[1]
+    _check(load().procmv_plan_choose(int(planner), ctypes.byref(mm) if mm is not None else None,
+                                     pp, nn, int(D), int(nvec), float(budget_bytes), int(reuse),
+                                     int(family), ctypes.byref(idx), ctypes.byref(sc)))
+    return idx.value, sc.value
+
+
+def mlp_param_count():
+    return int(load().procmv_mlp_param_count())
+
+
+def mlp_grad(params, z, t):
+    """Gradient and loss of one GPU forward/backward pass (test hook)."""
+    p, pp = _f32(params)
+    zz, zp = _f32(z)
+    tt, tp = _f32(t)
+    g = np.zeros(mlp_param_count(), np.float32)
+    loss = np.zeros(1, np.float32)
+    _check(load().procmv_mlp_grad(pp, zp, tp, int(tt.size),
+                                  g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                  loss.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return g, float(loss[0])
+
+
+def mlp_train(z, t, params, epochs, lr):
+    """Full-batch Adam on the GPU; returns (params, loss history)."""
+    zz, zp = _f32(z)
+    tt, tp = _f32(t)
+    p = np.array(params, dtype=np.float32, copy=True)
+    hist = np.zeros(max(epochs, 1), np.float32)
+    _check(load().procmv_mlp_train(zp, tp, int(tt.size), int(epochs), float(lr),
+                                   p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                   hist.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return p, hist[:epochs]
+
+
+def mlp_predict(params, z):
+    p, pp = _f32(params)
+    zz, zp = _f32(z)
+    y = np.zeros(zz.shape[0], np.float32)
+    _check(load().procmv_mlp_predict(pp, zp, int(zz.shape[0]),
+                                     y.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return y
+
+
+def measure(gen, D, nvec, block_size, strategy, cache_fraction=0.0,
+            precision=FP32, seed=1, warmup=1, reps=2, stream=None):
+    """Library-measured (t_fill_ms, t_apply_ms) of one operator and plan;
+    None when the plan does not fit in device memory."""
+    tf, ta = ctypes.c_double(), ctypes.c_double()
+    st = load().procmv_measure(gen, ctypes.c_uint64(seed), int(D), None, int(nvec),
+                               int(block_size), int(strategy), float(cache_fraction),
+                               int(precision), int(warmup), int(reps), _stream(stream),
+                               ctypes.byref(tf), ctypes.byref(ta))
+    if st == 2:
+        return None
+    _check(st)
+    return tf.value, ta.value
 
 
 class Operator:

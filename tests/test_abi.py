@@ -58,3 +58,42 @@ def test_invalid_arguments_rejected_on_host():
     assert L.procmv_get_entries(h, 90, 0, 20, 1, x, None) == 1  # window outside
     L.procmv_destroy(h)
     L.procmv_destroy(None)
+
+
+def test_planner_memory_model_matches_paper_formulas():
+    """Cache bytes of a plan are Eq. planner_partial_cache over canonical pairs
+    (Eq. partial_cache_pairs); the memory test is Eq. planner_memory_constraint."""
+    from paper_2606_31598_amd import procmv as pm
+    from oracle import planner as opl
+    D, b = 262144, 512
+    nb = D // b
+    for st, f in ((1, 0.25), (2, 1.0), (0, 0.0)):
+        x, mt, fe = pm.plan_features(D, 16, 256e9, 1, 0, b, st, f)
+        p = {0: 0, 1: int(f * opl.n_pair(nb)), 2: opl.n_pair(nb)}[st]
+        m_op = opl.mem_partial(p, b)
+        # workspace (Eq. planner_workspace, r arrays of D x R complex64): the
+        # partial slots (one per 256-row band + 1, R = 16 per block of vectors)
+        # plus input and output
+        m_work = opl.mem_work(D // 256 + 1, D, 16) + opl.mem_work(2, D, 16)
+        assert mt == m_op + m_work
+        assert fe == opl.feasible(mt, [256e9], alpha=0.9)
+        assert abs(x[7] - mt / 256e9) < 1e-6
+    # a GUE full cache at D = 2^18 does not fit 256 GB
+    _, _, fe = pm.plan_features(D, 1, 256e9, 1, 0, b, 2, 1.0)
+    assert not fe
+
+
+def test_analytic_planner_prefers_cache_with_reuse():
+    from paper_2606_31598_amd import procmv as pm
+    mm = pm.MachineModel()
+    mm.gen_rate[0], mm.gen_rate[1] = 2.7e11, 5e11
+    mm.dvr_rate, mm.cache_bw, mm.flop_rate, mm.launch_s = 1.4e13, 4e12, 1e14, 2e-5
+    c = pm.plan_candidates()
+    q1, _ = pm.plan_choose(0, 32768, 1, 256e9, 1, 0, mm=mm)
+    q500, _ = pm.plan_choose(0, 32768, 1, 256e9, 500, 0, mm=mm)
+    assert c[q1][1] == pm.PROCEDURAL        # one product: filling a cache never pays
+    assert c[q500][1] == pm.FULL            # many products: the full cache does
+    import pytest as _pt
+    with _pt.raises(pm.ProcmvError) as e:
+        pm.plan_choose(0, 262144, 64, 1e6, 1, 0, mm=mm)
+    assert e.value.status == 3

@@ -1,0 +1,85 @@
+"""GPU checks of the planner surrogate and of the trained planner.
+
+The hand-written MLP kernels must reproduce the binary64 oracle's gradients;
+training on the GPU must fit; and on held-out workloads the trained network
+must choose better plans than the fixed procedural plan (exhaustive measured
+search is the judge).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import planner as opl
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DATA = os.path.join(ROOT, "paper_2606_31598_amd", "data")
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_31598_amd import procmv
+    procmv.load()
+    return procmv
+
+
+def _pack(p):
+    return np.concatenate([p["W1"].ravel(), p["b1"], p["W2"].ravel(), p["b2"],
+                           p["W3"].ravel(), p["b3"]])
+
+
+def test_mlp_gradients_match_oracle(pm):
+    rng = np.random.default_rng(5)
+    p = opl.mlp_init(seed=3)
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.standard_normal(p[k].shape) * 0.1
+    z = rng.standard_normal((300, 8))
+    t = rng.standard_normal(300)
+    loss64, g64 = opl.mlp_loss_grad(p, z, t)
+    g32, loss32 = pm.mlp_grad(_pack(p), z, t)
+    ref = _pack(g64)
+    assert abs(loss32 - loss64) <= 1e-5 * max(1.0, loss64)
+    assert np.linalg.norm(g32 - ref) <= 1e-4 * np.linalg.norm(ref)
+    for k, sl in (("W1", slice(0, 512)), ("W2", slice(576, 576 + 4096)), ("b3", slice(-1, None))):
+        assert np.allclose(g32[sl], ref[sl], rtol=1e-3, atol=1e-6 * np.abs(ref).max())
+
+
+def test_mlp_training_fits(pm):
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1, 1, (512, 8))
+    y = np.sin(x[:, 0]) + 0.5 * x[:, 1] * x[:, 2]
+    p = _pack(opl.mlp_init(seed=2))
+    params, hist = pm.mlp_train(x, y, p, 1500, 3e-3)
+    assert hist[-1] < 0.02 * hist[0]
+    pred = pm.mlp_predict(params, x)
+    # forward pass of the trained parameters in binary64 (oracle)
+    q = {}
+    o = 0
+    for name, shape in (("W1", (8, 64)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)),
+                        ("W3", (64, 1)), ("b3", (1,))):
+        n = int(np.prod(shape))
+        q[name] = params[o:o + n].astype(np.float64).reshape(shape)
+        o += n
+    ref, _ = opl.mlp_forward(q, x)
+    assert np.max(np.abs(pred - ref)) < 1e-4
+
+
+def test_trained_planner_beats_fixed_plan(pm):
+    trials = os.path.join(DATA, "mi355x_plan_trials.jsonl")
+    model_path = os.path.join(DATA, "mi355x_planner_mlp.json")
+    if not (os.path.exists(trials) and os.path.exists(model_path)):
+        pytest.skip("no measured plan trials / trained model committed")
+    from paper_2606_31598_amd import planner
+    mm, table = planner.load_trials(trials)
+    model = json.load(open(model_path))
+    res = planner.evaluate(table, mm, model, n=200)
+    print(json.dumps(res))
+    assert res["n_workloads"] >= 150
+    assert res["learned"]["mean_regret"] < res["procedural"]["mean_regret"]
+    assert res["learned"]["within_10pct"] >= res["procedural"]["within_10pct"]
