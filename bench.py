@@ -35,6 +35,31 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "dvr_toeplitz_D32768_pmc.txt")
+DVR_SOURCE = os.path.join(ROOT, "paper_2606_31598_amd", "csrc", "dvr.hip")
+
+
+def counted_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    vals = {}
+    for line in open(PMC_SUMMARY):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(DVR_SOURCE, "rb").read()).hexdigest()
+    if vals.get("source_sha256") != digest:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def measure_apply(pm, op, X, reps, warm=2):
     """Mean seconds per product over `reps` products (HIP events)."""
     import torch
@@ -156,7 +181,8 @@ def run_dvr(args):
                            "sampled_every": args.profile_every},
         "roofline": {"bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": counted_traffic()},
     }
 
     if args.modes:

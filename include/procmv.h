@@ -175,6 +175,12 @@ procmv_status procmv_profile_read(procmv_op_t H, double* tile_ms,
 procmv_status procmv_autotune(procmv_op_t H, int32_t nvec, int32_t reps,
                               void* stream, int32_t* shape_out, double* best_ms);
 
+/* Set the VALU tile shape (0, 1, 2: 8, 16, 32 direct values per lane and
+ * vector block) explicitly.  Products are bit-identical across storage modes
+ * and block sizes for one tile shape; procmv_plan resets the shape to its
+ * default (2 without cache, 0 with one). */
+procmv_status procmv_set_tile_shape(procmv_op_t H, int32_t shape);
+
 /* Measured microbenchmark of one (operator, plan) pair (paper Sec. IV-C,
  * Eq. measured_matvec_time): creates the operator, times procmv_plan
  * (allocation and cache fill) and the mean of `reps` products of nvec
@@ -201,9 +207,10 @@ procmv_status procmv_plan_candidate(int32_t idx, int32_t* block_size,
                                     int32_t* strategy, double* cache_fraction);
 
 /* Surrogate features of (problem, plan) (paper Sec. IV-D, feature vector
- * x(p); this library's 8): log2 D, log2 nvec, log2 budget[GB], log2 reuse,
+ * x(p); this library's 8): log2 D, log2 nvec, log2(1 + cache MB), log2 reuse,
  * family (0 GUE, 1 DVR), log2 b, cached fraction (procedural 0, full 1),
- * M_tot / budget.  x_out: 8 floats (host).  *feasible_out = memory test. */
+ * M_tot / budget (the budget enters through this ratio and the memory test).
+ * x_out: 8 floats (host).  *feasible_out = memory test. */
 procmv_status procmv_plan_features(int64_t D, int32_t nvec, double budget_bytes,
                                    int64_t reuse, int32_t family,
                                    int32_t block_size, int32_t strategy,

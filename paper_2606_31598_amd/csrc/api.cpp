@@ -292,9 +292,9 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
     const size_t need = (size_t)out.n_slots * out.nv_stride * ldp * sizeof(float2);
     procmv_status st = ensure(op->d_P, op->P_bytes, need);
     if (st != PROCMV_OK) return st;
-    hipEvent_t e0, e1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool timed = op->prof_pair(0, e0, e1);
-    if (timed) HIP_TRY(hipEventRecord(e0, s));
+    if (timed && !toeplitz) HIP_TRY(hipEventRecord(e0, s));
     if (toeplitz) {
         DvrToeplitzArgs a{};
         a.D = (int32_t)op->D;
@@ -303,7 +303,7 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
         a.ldx = ldx;
         a.P = op->d_P;
         a.ldp = (int64_t)ldp;
-        HIP_TRY(launch_dvr_toeplitz(a, nv, variant, s));
+        HIP_TRY(launch_dvr_toeplitz(a, nv, variant, s, timed ? e0 : nullptr, e1));
     } else {
         TileArgs a{};
         a.src = op->source();
@@ -319,18 +319,16 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
                                            (int)op->n_st, s));
         else HIP_TRY(launch_tile_apply(a, nv, op->tile_shape, (int)op->n_st, s));
     }
-    if (timed) HIP_TRY(hipEventRecord(e1, s));
+    if (timed && !toeplitz) HIP_TRY(hipEventRecord(e1, s));
     return PROCMV_OK;
 }
 
 procmv_status run_reduce(procmv_op* op, const ReduceArgs& r, Epi mode,
                          hipStream_t s)
 {
-    hipEvent_t e0, e1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool timed = op->prof_pair(1, e0, e1);
-    if (timed) HIP_TRY(hipEventRecord(e0, s));
-    HIP_TRY(launch_reduce(r, mode, s));
-    if (timed) HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(launch_reduce(r, mode, s, timed ? e0 : nullptr, e1));
     return PROCMV_OK;
 }
 
@@ -933,6 +931,9 @@ procmv_status procmv_batch_create(const procmv_op_t* ops, int32_t n, int32_t nve
     BTRY(hipMalloc((void**)&B->d_off, n * sizeof(int64_t)));
     BTRY(hipMemcpy(B->d_off, B->off.data(), n * sizeof(int64_t), hipMemcpyHostToDevice));
 #undef BTRY
+    bool any_cache = false;
+    for (procmv_op* op : B->ops) any_cache |= op->p_cache > 0;
+    B->shape = any_cache ? 0 : 2;   // same default rule as single operators
     st = batch_upload_items(B);
     if (st != PROCMV_OK) {
         delete B;
@@ -1141,6 +1142,15 @@ procmv_status procmv_batch_propagate(procmv_batch_t B, void* psi, double dt, int
     return PROCMV_OK;
 }
 
+procmv_status procmv_set_tile_shape(procmv_op_t H, int32_t shape)
+{
+    procmv_status st = check_op(H);
+    if (st != PROCMV_OK) return st;
+    if (shape < 0 || shape > 2) return fail(PROCMV_ERR_INVALID_ARG, "tile shape %d", shape);
+    H->tile_shape = shape;
+    return PROCMV_OK;
+}
+
 procmv_status procmv_autotune(procmv_op_t H, int32_t nvec, int32_t reps, void* stream,
                               int32_t* shape_out, double* best_ms)
 {
@@ -1220,9 +1230,14 @@ procmv_status procmv_measure(procmv_generator gen, uint64_t seed, int64_t D,
         if (Y) (void)hipFree(Y);
         procmv_destroy(H);
     };
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        cleanup();
-        return fail(PROCMV_ERR_HIP, "event creation failed");
+    {
+        hipError_t ee = hipFree(nullptr);   // make sure the device context exists
+        if (ee == hipSuccess) ee = hipEventCreate(&e0);
+        if (ee == hipSuccess) ee = hipEventCreate(&e1);
+        if (ee != hipSuccess) {
+            cleanup();
+            return fail(PROCMV_ERR_HIP, "event creation failed: %s", hipGetErrorString(ee));
+        }
     }
     // fill time: the plan call (allocation + cache fill, synchronised)
     if (hipEventRecord(e0, s) != hipSuccess) { cleanup(); return fail(PROCMV_ERR_HIP, "event"); }
@@ -1403,7 +1418,7 @@ void plan_features(int64_t D, int32_t nvec, double budget, int64_t reuse, int fa
     plan_memory(D, nvec, family, b, strategy, f, reuse, mo, mw);
     x[0] = (float)std::log2((double)D);
     x[1] = (float)std::log2((double)nvec);
-    x[2] = (float)std::log2(budget / 1e9);
+    x[2] = (float)std::log2(1.0 + mo / 1e6);          // cache size (MB): fill work
     x[3] = (float)std::log2((double)reuse);
     x[4] = (float)family;
     x[5] = (float)std::log2((double)b);

@@ -15,6 +15,8 @@
 // Both go to a partial buffer in which every output element has exactly one
 // slot per super-tile band (see kSuper), and a second kernel sums the slots
 // in a fixed order: no atomics, bit-reproducible results.
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 
 namespace procmv {
@@ -484,21 +486,20 @@ hipError_t launch_tile_apply_batched(const BatchTileLaunch& b, hipStream_t s)
 #undef PROCMV_SHAPES
 }
 
-hipError_t launch_reduce(const ReduceArgs& a, Epi mode, hipStream_t s)
+hipError_t launch_reduce(const ReduceArgs& a, Epi mode, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1)
 {
     const int64_t total = (int64_t)a.nv * a.D;
-    const dim3 grid((unsigned)((total + 63) / 64));
+    const dim3 grid((unsigned)((total + 63) / 64)), blk(256);
+#define PROCMV_RED(M)                                                                   \
+    if (e0) hipExtLaunchKernelGGL(reduce_kernel<M>, grid, blk, 0, s, e0, e1, 0, a);     \
+    else hipLaunchKernelGGL(reduce_kernel<M>, grid, blk, 0, s, a);
     switch (mode) {
-    case Epi::kApply:
-        hipLaunchKernelGGL(reduce_kernel<Epi::kApply>, grid, dim3(256), 0, s, a);
-        break;
-    case Epi::kChebFirst:
-        hipLaunchKernelGGL(reduce_kernel<Epi::kChebFirst>, grid, dim3(256), 0, s, a);
-        break;
-    case Epi::kChebStep:
-        hipLaunchKernelGGL(reduce_kernel<Epi::kChebStep>, grid, dim3(256), 0, s, a);
-        break;
+    case Epi::kApply: PROCMV_RED(Epi::kApply) break;
+    case Epi::kChebFirst: PROCMV_RED(Epi::kChebFirst) break;
+    case Epi::kChebStep: PROCMV_RED(Epi::kChebStep) break;
     }
+#undef PROCMV_RED
     return hipGetLastError();
 }
 

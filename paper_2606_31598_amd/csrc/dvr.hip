@@ -11,6 +11,8 @@
 // carried in registers (a sliding window).  The zero-diagonal Toeplitz sum of each column chunk
 // goes to one partial slot; the fixed-order reduction adds the chunks, the
 // site potential v_i x_i and the constant diagonal.
+#include <hip/hip_ext.h>
+
 #include <cstdlib>
 
 #include "kernels.h"
@@ -130,29 +132,34 @@ __global__ __launch_bounds__(256) void dvr_toeplitz_kernel(DvrToeplitzArgs a)
 }
 
 template <int NV, int RB, int CHUNK, int CS, int XL>
-hipError_t launch_cfg(const DvrToeplitzArgs& a, hipStream_t s)
+hipError_t launch_cfg(const DvrToeplitzArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 grid((unsigned)((a.D + 256 * RB - 1) / (256 * RB)),
                     (unsigned)((a.D + CHUNK - 1) / CHUNK));
-    hipLaunchKernelGGL((dvr_toeplitz_kernel<NV, RB, CHUNK, CS, XL>), grid, dim3(256), 0, s, a);
+    if (e0)   // events stamped by the dispatch itself (kernel start / end)
+        hipExtLaunchKernelGGL((dvr_toeplitz_kernel<NV, RB, CHUNK, CS, XL>), grid, dim3(256), 0,
+                              s, e0, e1, 0, a);
+    else
+        hipLaunchKernelGGL((dvr_toeplitz_kernel<NV, RB, CHUNK, CS, XL>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 // Variants: (rows per lane, chunk, columns per step, x in LDS).
 template <int NV>
-hipError_t launch_dvr_nv(const DvrToeplitzArgs& a, int variant, hipStream_t s)
+hipError_t launch_dvr_nv(const DvrToeplitzArgs& a, int variant, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1)
 {
     switch (variant) {
-    case 0: return launch_cfg<NV, 4, 256, 8, 0>(a, s);
-    case 1: return launch_cfg<NV, 4, 1024, 8, 0>(a, s);
-    case 2: return launch_cfg<NV, 4, 1024, 16, 0>(a, s);
-    case 3: return launch_cfg<NV, 4, 1024, 8, 1>(a, s);
-    case 4: return launch_cfg<NV, 8, 512, 8, 1>(a, s);
-    case 5: return launch_cfg<NV, 8, 1024, 16, 0>(a, s);
-    case 6: return launch_cfg<NV, 4, 512, 16, 1>(a, s);
-    case 7: return launch_cfg<NV, 8, 512, 16, 1>(a, s);
-    case 8: return launch_cfg<NV, 8, 256, 16, 1>(a, s);
-    case 9: return launch_cfg<NV, 4, 256, 16, 1>(a, s);
+    case 0: return launch_cfg<NV, 4, 256, 8, 0>(a, s, e0, e1);
+    case 1: return launch_cfg<NV, 4, 1024, 8, 0>(a, s, e0, e1);
+    case 2: return launch_cfg<NV, 4, 1024, 16, 0>(a, s, e0, e1);
+    case 3: return launch_cfg<NV, 4, 1024, 8, 1>(a, s, e0, e1);
+    case 4: return launch_cfg<NV, 8, 512, 8, 1>(a, s, e0, e1);
+    case 5: return launch_cfg<NV, 8, 1024, 16, 0>(a, s, e0, e1);
+    case 6: return launch_cfg<NV, 4, 512, 16, 1>(a, s, e0, e1);
+    case 7: return launch_cfg<NV, 8, 512, 16, 1>(a, s, e0, e1);
+    case 8: return launch_cfg<NV, 8, 256, 16, 1>(a, s, e0, e1);
+    case 9: return launch_cfg<NV, 4, 256, 16, 1>(a, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -174,13 +181,13 @@ int dvr_toeplitz_chunk_of(int variant)
 }
 
 hipError_t launch_dvr_toeplitz(const DvrToeplitzArgs& a, int nv, int variant,
-                               hipStream_t s)
+                               hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     switch (nv) {
-    case 1: return launch_dvr_nv<1>(a, variant, s);
-    case 2: return launch_dvr_nv<2>(a, variant, s);
-    case 4: return launch_dvr_nv<4>(a, variant, s);
-    case 8: return launch_dvr_nv<8>(a, variant, s);
+    case 1: return launch_dvr_nv<1>(a, variant, s, e0, e1);
+    case 2: return launch_dvr_nv<2>(a, variant, s, e0, e1);
+    case 4: return launch_dvr_nv<4>(a, variant, s, e0, e1);
+    case 8: return launch_dvr_nv<8>(a, variant, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }

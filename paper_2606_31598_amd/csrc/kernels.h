@@ -122,7 +122,8 @@ constexpr int kMlpParams = kMlpIn * kMlpHidden + kMlpHidden + kMlpHidden * kMlpH
 hipError_t launch_tile_apply(const TileArgs& a, int nv, int shape, int n_st,
                              hipStream_t s);
 hipError_t launch_tile_apply_batched(const BatchTileLaunch& b, hipStream_t s);
-hipError_t launch_reduce(const ReduceArgs& a, Epi mode, hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs& a, Epi mode, hipStream_t s,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // MFMA multi-vector tile product, nv <= 16 (defined in mfma.hip);
 // precision 0 = binary32 MFMA, 1 = split bfloat16.
 hipError_t launch_tile_mfma(const TileArgs& a, int precision, int n_st,
@@ -136,8 +137,10 @@ hipError_t launch_get_entries(const SourceArgs& src, int64_t r0, int64_t c0,
 // Sinc-DVR Toeplitz product (defined in dvr.hip).
 int dvr_toeplitz_variant(int32_t D);
 int dvr_toeplitz_chunk_of(int variant);
+// e0/e1 (optional): start/stop events recorded by the kernel's dispatch.
 hipError_t launch_dvr_toeplitz(const DvrToeplitzArgs& a, int nv, int variant,
-                               hipStream_t s);
+                               hipStream_t s, hipEvent_t e0 = nullptr,
+                               hipEvent_t e1 = nullptr);
 // Batched reduction and completion (defined in batch.hip).
 hipError_t launch_reduce_batched(const BatchReduceArgs& a, Epi mode, hipStream_t s);
 hipError_t launch_finish_batched(const BatchReduceItem* items, int n, int nv,

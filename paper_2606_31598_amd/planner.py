@@ -72,6 +72,8 @@ def model_from(d):
 def collect(out_path, log2_d=LOG2_D, nvecs=NVECS, families=(0, 1), reps=2):
     """Measure fill and product time of every memory-feasible candidate on the
     (D, nvec, family) grid; one JSON line per trial."""
+    import torch
+    torch.zeros(1, device="cuda")       # initialise the device before timing
     cands = pm.plan_candidates()
     n = 0
     with open(out_path, "w") as fh:
@@ -208,11 +210,16 @@ def main(argv=None):
     ap.add_argument("--trials", default=DEFAULT_TRIALS)
     ap.add_argument("--out", default=None)
     ap.add_argument("--model", default=DEFAULT_MODEL)
+    ap.add_argument("--min-log2d", type=int, default=12)
+    ap.add_argument("--families", default="0,1")
+    ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--max-log2d", type=int, default=18)
     args = ap.parse_args(argv)
     if args.cmd in ("collect", "all"):
         out = args.out or args.trials
-        n = collect(out, log2_d=range(12, args.max_log2d + 1))
+        fams = tuple(int(f) for f in args.families.split(","))
+        n = collect(out, log2_d=range(args.min_log2d, args.max_log2d + 1), families=fams,
+                    reps=args.reps)
         log(f"{n} trials written to {out}")
         args.trials = out
     if args.cmd in ("train", "all"):

@@ -31,7 +31,7 @@ EXPORTS = [
     "procmv_measure", "procmv_plan_candidate_count", "procmv_plan_candidate",
     "procmv_plan_features", "procmv_plan_model_time", "procmv_plan_choose",
     "procmv_plan_auto", "procmv_mlp_param_count", "procmv_mlp_grad",
-    "procmv_mlp_train", "procmv_mlp_predict",
+    "procmv_mlp_train", "procmv_mlp_predict", "procmv_set_tile_shape",
 ]
 
 
@@ -129,6 +129,7 @@ def load():
                                      c.c_int32, i32p, f64p]
     L.procmv_plan_auto.argtypes = [vp, c.c_int32, c.c_double, c.c_int64, c.c_int32,
                                    c.POINTER(MachineModel), f32p, f32p, vp, i32p]
+    L.procmv_set_tile_shape.argtypes = [vp, c.c_int32]
     L.procmv_mlp_param_count.restype = c.c_int32
     L.procmv_mlp_grad.argtypes = [f32p, f32p, f32p, c.c_int32, f32p, f32p]
     L.procmv_mlp_train.argtypes = [f32p, f32p, c.c_int32, c.c_int32, c.c_float, f32p, f32p]
@@ -375,6 +376,10 @@ class Operator:
         _check(load().procmv_autotune(self._h, int(nvec), int(reps), _stream(stream),
                                       ctypes.byref(sh), ctypes.byref(ms)))
         return sh.value, ms.value
+
+    def set_tile_shape(self, shape):
+        _check(load().procmv_set_tile_shape(self._h, int(shape)))
+        return self
 
     def entries(self, r0, c0, nr, nc, stream=None):
         """Generated binary32 entries of a window, as a complex64 CUDA tensor."""

@@ -44,7 +44,7 @@ def test_gue_propagation_cached_identical(pm):
     psi0 = to_dev(workloads.gaussian_vectors(D, 2, seed=1))
     outs = []
     for strat, f in [(pm.PROCEDURAL, 0), (pm.PARTIAL, 0.5), (pm.FULL, 1)]:
-        op = pm.Operator.gue(D, seed=2).plan(128, strat, f)
+        op = pm.Operator.gue(D, seed=2).plan(128, strat, f).set_tile_shape(1)
         P = psi0.clone()
         op.propagate(P, 0.05, nsteps=5)
         outs.append(to_host(P))
