@@ -346,6 +346,30 @@ ReduceArgs reduce_args(procmv_op* op, int nv, const TileOut& t)
     return r;
 }
 
+// One product H X of a vector block, reduced with the epilogue `mode`: tile
+// kernel, then the fixed-order reduction.  r carries the epilogue operands
+// (X, Y, acc, alpha, beta, coefficients); the partial-buffer fields are
+// filled here.
+procmv_status run_product(procmv_op* op, const float2* X, int64_t ldx, int nv, ReduceArgs r,
+                          Epi mode, hipStream_t s)
+{
+    TileOut to;
+    procmv_status st = run_tiles(op, X, ldx, nv, s, to);
+    if (st != PROCMV_OK) return st;
+    ReduceArgs base = reduce_args(op, nv, to);
+    r.D = base.D;
+    r.nv = base.nv;
+    r.nv_stride = base.nv_stride;
+    r.n_slots = base.n_slots;
+    r.P = base.P;
+    r.ldp = base.ldp;
+    r.vdiag = base.vdiag;
+    r.X = X;
+    r.ldx = ldx;
+    return run_reduce(op, r, mode, s);
+}
+
+
 
 }  // namespace
 
@@ -509,17 +533,13 @@ procmv_status procmv_apply(procmv_op_t H, const void* X, int64_t ldx, void* Y,
         const int nv = chunk_vectors(H, nvec - v0);
         const float2* Xc = (const float2*)X + (size_t)v0 * ldx;
         float2* Yc = (float2*)Y + (size_t)v0 * ldy;
-        TileOut to;
-        st = run_tiles(H, Xc, ldx, nv, s, to);
-        if (st != PROCMV_OK) return st;
-        ReduceArgs r = reduce_args(H, nv, to);
-        r.X = Xc;
-        r.ldx = ldx;
+        ReduceArgs r{};
         r.Y = Yc;
         r.ldy = ldy;
+        r.alpha = 1.0f;
         r.beta_hi = bhi;
         r.beta_lo = blo;
-        st = run_reduce(H, r, Epi::kApply, s);
+        st = run_product(H, Xc, ldx, nv, r, Epi::kApply, s);
         if (st != PROCMV_OK) return st;
         v0 += nv;
     }
@@ -607,12 +627,7 @@ procmv_status procmv_chebyshev_propagate(procmv_op_t H, void* psi, int64_t ld,
             int64_t lda = ld;
             float2* qb = H->d_q;
             int64_t ldb = (int64_t)D;
-            TileOut to;
-            st = run_tiles(H, qa, lda, nv, s, to);
-            if (st != PROCMV_OK) return st;
-            ReduceArgs r = reduce_args(H, nv, to);
-            r.X = qa;
-            r.ldx = lda;
+            ReduceArgs r{};
             r.Yq1 = qb;
             r.ldy = ldb;
             r.acc = H->d_acc;
@@ -622,7 +637,7 @@ procmv_status procmv_chebyshev_propagate(procmv_op_t H, void* psi, int64_t ld,
             r.beta_lo = blo;
             r.a0 = a[0];
             r.a1 = a[1];
-            st = run_reduce(H, r, Epi::kChebFirst, s);
+            st = run_product(H, qa, lda, nv, r, Epi::kChebFirst, s);
             if (st != PROCMV_OK) return st;
             // cur = qb (q1), prev = qa (q0)
             float2* cur = qb;
@@ -630,11 +645,7 @@ procmv_status procmv_chebyshev_propagate(procmv_op_t H, void* psi, int64_t ld,
             float2* prev = qa;
             int64_t ldpv = lda;
             for (int k = 1; k < K; ++k) {
-                st = run_tiles(H, cur, ldc, nv, s, to);
-                if (st != PROCMV_OK) return st;
-                ReduceArgs rs = reduce_args(H, nv, to);
-                rs.X = cur;
-                rs.ldx = ldc;
+                ReduceArgs rs{};
                 rs.Y = prev;   // q_{k-1} in, q_{k+1} out
                 rs.ldy = ldpv;
                 rs.acc = H->d_acc;
@@ -643,7 +654,7 @@ procmv_status procmv_chebyshev_propagate(procmv_op_t H, void* psi, int64_t ld,
                 rs.beta_hi = bhi;
                 rs.beta_lo = blo;
                 rs.a0 = a[k + 1];
-                st = run_reduce(H, rs, Epi::kChebStep, s);
+                st = run_product(H, cur, ldc, nv, rs, Epi::kChebStep, s);
                 if (st != PROCMV_OK) return st;
                 std::swap(cur, prev);
                 std::swap(ldc, ldpv);

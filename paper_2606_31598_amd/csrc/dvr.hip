@@ -22,7 +22,7 @@ namespace procmv {
 namespace {
 
 template <int NV, int RB, int CHUNK, int CS, int XL>
-__global__ __launch_bounds__(256) void dvr_toeplitz_kernel(DvrToeplitzArgs a)
+__device__ __forceinline__ void dvr_band_chunk(const DvrToeplitzArgs& a)
 {
     // CS columns per step; XL = 1 stages the chunk's x in LDS (broadcast
     // reads), XL = 0 reads it through the scalar cache.
@@ -129,6 +129,12 @@ __global__ __launch_bounds__(256) void dvr_toeplitz_kernel(DvrToeplitzArgs a)
                 a.P[((size_t)chunk * NV + v) * a.ldp + i] = acc[r][v];
         }
     }
+}
+
+template <int NV, int RB, int CHUNK, int CS, int XL>
+__global__ __launch_bounds__(256) void dvr_toeplitz_kernel(DvrToeplitzArgs a)
+{
+    dvr_band_chunk<NV, RB, CHUNK, CS, XL>(a);
 }
 
 template <int NV, int RB, int CHUNK, int CS, int XL>

@@ -88,6 +88,48 @@ struct ReduceArgs {
     double2 a0, a1;           // Chebyshev coefficients of the epilogue
 };
 
+// Epilogue of the fixed-order reduction for output element (v, i) whose
+// summed partials are (sx, sy): add the site diagonal, scale, add the
+// constant diagonal, then store (product) or advance the Chebyshev
+// recurrence and the binary64 accumulator.
+template <Epi MODE>
+__device__ __forceinline__ void reduce_epilogue(const ReduceArgs& a, int v, int i, float sx,
+                                                float sy)
+{
+    const float2 x = a.X[v * a.ldx + i];
+    if (a.vdiag != nullptr) {
+        const float vd = a.vdiag[i];
+        sx = __builtin_fmaf(vd, x.x, sx);
+        sy = __builtin_fmaf(vd, x.y, sy);
+    }
+    // h = alpha * y + (beta_hi + beta_lo) * x
+    const float bx = __builtin_fmaf(a.beta_hi, x.x, a.beta_lo * x.x);
+    const float by = __builtin_fmaf(a.beta_hi, x.y, a.beta_lo * x.y);
+    const float hx = __builtin_fmaf(a.alpha, sx, bx);
+    const float hy = __builtin_fmaf(a.alpha, sy, by);
+    if (MODE == Epi::kApply) {
+        a.Y[v * a.ldy + i] = make_float2(hx, hy);
+    } else if (MODE == Epi::kChebFirst) {
+        a.Yq1[v * a.ldy + i] = make_float2(hx, hy);
+        double2 r;
+        r.x = a.a0.x * (double)x.x - a.a0.y * (double)x.y;
+        r.y = a.a0.x * (double)x.y + a.a0.y * (double)x.x;
+        r.x += a.a1.x * (double)hx - a.a1.y * (double)hy;
+        r.y += a.a1.x * (double)hy + a.a1.y * (double)hx;
+        a.acc[v * a.ldacc + i] = r;
+    } else {
+        float2* qp = a.Y + v * a.ldy + i;
+        const float2 prev = *qp;
+        const float nx = __builtin_fmaf(2.0f, hx, -prev.x);
+        const float ny = __builtin_fmaf(2.0f, hy, -prev.y);
+        *qp = make_float2(nx, ny);
+        double2 r = a.acc[v * a.ldacc + i];
+        r.x += a.a0.x * (double)nx - a.a0.y * (double)ny;
+        r.y += a.a0.x * (double)ny + a.a0.y * (double)nx;
+        a.acc[v * a.ldacc + i] = r;
+    }
+}
+
 // Batched reduction: per-instance description and the launch arguments.
 struct BatchReduceItem {
     int32_t D;
