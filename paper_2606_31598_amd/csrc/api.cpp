@@ -284,7 +284,7 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
     const size_t ldp = (size_t)op->D;
     const bool mfma = use_mfma(op, nv);
     const bool toeplitz = !mfma && op->gen == 1 && op->p_cache == 0;
-    const int variant = toeplitz ? dvr_toeplitz_variant((int32_t)op->D) : 0;
+    const int variant = toeplitz ? dvr_toeplitz_variant((int32_t)op->D, nv) : 0;
     const int chunk = toeplitz ? dvr_toeplitz_chunk_of(variant) : 1;
     out.n_slots = toeplitz ? (int32_t)((op->D + chunk - 1) / chunk) : op->n_super + 1;
     out.vdiag = toeplitz ? op->d_v : nullptr;

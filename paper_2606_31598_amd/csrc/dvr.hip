@@ -166,24 +166,31 @@ hipError_t launch_dvr_nv(const DvrToeplitzArgs& a, int variant, hipStream_t s, h
     case 7: return launch_cfg<NV, 8, 512, 16, 1>(a, s, e0, e1);
     case 8: return launch_cfg<NV, 8, 256, 16, 1>(a, s, e0, e1);
     case 9: return launch_cfg<NV, 4, 256, 16, 1>(a, s, e0, e1);
+    case 10: return launch_cfg<NV, 4, 1024, 16, 1>(a, s, e0, e1);
+    case 11: return launch_cfg<NV, 8, 1024, 16, 1>(a, s, e0, e1);
+    case 12: return launch_cfg<NV, 4, 1024, 32, 1>(a, s, e0, e1);
+    case 13: return launch_cfg<NV, 4, 2048, 16, 1>(a, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-int dvr_toeplitz_variant(int32_t D)
+int dvr_toeplitz_variant(int32_t D, int nv)
 {
     if (const char* e = getenv("PROCMV_DVR_VARIANT")) return atoi(e);
     // measured on MI355X: x staged in LDS, 4 rows per lane, 16 columns per
-    // step; 512-column chunks at large D, 256 below
-    return D >= 16384 ? 6 : 9;
+    // step; at large D 1024-column chunks for one vector (half the partial
+    // slots of 512) and 512 for more; 256-column chunks below
+    if (D < 16384) return 9;
+    return nv == 1 ? 10 : 6;
 }
 
 int dvr_toeplitz_chunk_of(int variant)
 {
-    static const int chunk[10] = {256, 1024, 1024, 1024, 512, 1024, 512, 512, 256, 256};
-    return (variant >= 0 && variant < 10) ? chunk[variant] : 0;
+    static const int chunk[14] = {256, 1024, 1024, 1024, 512, 1024, 512, 512, 256, 256,
+                                  1024, 1024, 1024, 2048};
+    return (variant >= 0 && variant < 14) ? chunk[variant] : 0;
 }
 
 hipError_t launch_dvr_toeplitz(const DvrToeplitzArgs& a, int nv, int variant,

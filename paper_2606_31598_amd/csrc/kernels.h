@@ -177,7 +177,7 @@ hipError_t launch_get_entries(const SourceArgs& src, int64_t r0, int64_t c0,
                               int32_t nr, int32_t nc, float2* out,
                               hipStream_t s);
 // Sinc-DVR Toeplitz product (defined in dvr.hip).
-int dvr_toeplitz_variant(int32_t D);
+int dvr_toeplitz_variant(int32_t D, int nv);
 int dvr_toeplitz_chunk_of(int variant);
 // e0/e1 (optional): start/stop events recorded by the kernel's dispatch.
 hipError_t launch_dvr_toeplitz(const DvrToeplitzArgs& a, int nv, int variant,
