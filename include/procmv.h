@@ -169,16 +169,20 @@ procmv_status procmv_profile_read(procmv_op_t H, double* tile_ms,
 
 /* Measured tile-shape tuning (paper Sec. IV-C, Algorithm 2, applied to the
  * kernel's launch shape): times `reps` products of nvec scratch vectors for
- * each VALU tile shape and keeps the fastest for this handle.  Allocates and
- * frees its scratch vectors; SYNCHRONISES the stream.  *shape_out / *best_ms
- * (host, may be NULL) receive the choice and its mean time per product. */
+ * each VALU tile shape (-1, 0, 1, 2; see procmv_set_tile_shape) and keeps the
+ * fastest for this handle.  Allocates and frees its scratch vectors;
+ * SYNCHRONISES the stream.  *shape_out / *best_ms (host, may be NULL) receive
+ * the choice and its mean time per product. */
 procmv_status procmv_autotune(procmv_op_t H, int32_t nvec, int32_t reps,
                               void* stream, int32_t* shape_out, double* best_ms);
 
 /* Set the VALU tile shape (0, 1, 2: 8, 16, 32 direct values per lane and
- * vector block) explicitly.  Products are bit-identical across storage modes
- * and block sizes for one tile shape; procmv_plan resets the shape to its
- * default (2 without cache, 0 with one). */
+ * vector block) explicitly, or -1 for the default that procmv_plan sets: the
+ * super-tiles whose canonical pairs are all cached use shape 0 (narrow tiles
+ * streaming the cache), those with none cached shape 2 for the Philox-GUE
+ * generator (wide tiles) and 0 for the sinc-DVR one, mixed ones (block size
+ * below 256) shape 0, one launch per class.  With one explicit shape, products are bit-identical across storage
+ * modes and block sizes. */
 procmv_status procmv_set_tile_shape(procmv_op_t H, int32_t shape);
 
 /* Measured microbenchmark of one (operator, plan) pair (paper Sec. IV-C,

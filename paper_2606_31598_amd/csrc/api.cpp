@@ -65,7 +65,7 @@ struct procmv_op {
     bool planned = false;
     int32_t b = 0, n_blk = 0;
     int strategy = 0, precision = 0;
-    int tile_shape = 1;       // VALU tile shape (see launch_tile_apply)
+    int tile_shape = -1;      // VALU tile shape (see launch_tile_apply); -1 = per class
     double frac = 0.0;
     int64_t n_pair = 0, p_cache = 0;
     int32_t* d_pair_slot = nullptr;
@@ -73,7 +73,9 @@ struct procmv_op {
     int2* d_pairs = nullptr;
     int32_t n_super = 0;
     int64_t n_st = 0;
-    int2* d_st = nullptr;
+    int2* d_st = nullptr;       // cached super-tiles, then generated, then mixed
+    int64_t n_st_cached = 0;    // super-tiles whose canonical pairs are all cached
+    int64_t n_st_gen = 0;       // super-tiles with no cached pair
     // workspace
     float2* d_P = nullptr;
     size_t P_bytes = 0;
@@ -105,6 +107,7 @@ struct procmv_op {
         s.slots = d_slots;
         s.b = b;
         s.n_blk = n_blk;
+        s.all_cached = (planned && p_cache > 0 && p_cache == n_pair) ? 1 : 0;
         return s;
     }
 
@@ -315,9 +318,38 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
         a.ldx = ldx;
         a.P = op->d_P;
         a.ldp = (int64_t)ldp;
-        if (mfma) HIP_TRY(launch_tile_mfma(a, op->precision == PROCMV_SPLIT_BF16 ? 1 : 0,
-                                           (int)op->n_st, s));
-        else HIP_TRY(launch_tile_apply(a, nv, op->tile_shape, (int)op->n_st, s));
+        if (mfma) {
+            HIP_TRY(launch_tile_mfma(a, op->precision == PROCMV_SPLIT_BF16 ? 1 : 0,
+                                     (int)op->n_st, s));
+        } else {
+            // one launch per super-tile class; the default shape streams the
+            // cache with narrow tiles and generates Philox entries with wide
+            // ones (sinc-DVR entries are table reads: narrow tiles)
+            const int64_t n_c = op->n_st_cached, n_g = op->n_st_gen;
+            const int64_t n_m = op->n_st - n_c - n_g;
+            const SourceArgs src = a.src;
+            if (n_c > 0) {
+                a.src.all_cached = 1;
+                HIP_TRY(launch_tile_apply(a, nv, op->tile_shape >= 0 ? op->tile_shape : 0,
+                                          (int)n_c, s));
+            }
+            if (n_g > 0) {
+                a.src = src;
+                a.src.pair_slot = nullptr;
+                a.src.all_cached = 0;
+                a.st_list = op->d_st + n_c;
+                const int gshape = op->gen == 0 ? 2 : 0;
+                HIP_TRY(launch_tile_apply(a, nv, op->tile_shape >= 0 ? op->tile_shape : gshape,
+                                          (int)n_g, s));
+            }
+            if (n_m > 0) {
+                a.src = src;
+                a.src.all_cached = 0;
+                a.st_list = op->d_st + n_c + n_g;
+                HIP_TRY(launch_tile_apply(a, nv, op->tile_shape >= 0 ? op->tile_shape : 0,
+                                          (int)n_m, s));
+            }
+        }
     }
     if (timed && !toeplitz) HIP_TRY(hipEventRecord(e1, s));
     return PROCMV_OK;
@@ -456,15 +488,35 @@ procmv_status procmv_plan(procmv_op_t H, int32_t block_size,
             }
         }
     H->p_cache = (int64_t)pairs.size();
-    // Default VALU tile shape (procmv_autotune refines it): wide tiles when
-    // generation dominates, narrow ones when the loop streams the cache.
-    H->tile_shape = H->p_cache > 0 ? 0 : 2;
-    // super-tile list
+    // VALU tile shape: per super-tile class unless set (procmv_autotune and
+    // procmv_set_tile_shape override it)
+    H->tile_shape = -1;
+    // super-tile list, grouped by how its canonical pairs are stored: all
+    // cached, none cached, or mixed (only when b < the super-tile edge)
     H->n_super = (int32_t)((D + kSuper - 1) / kSuper);
-    std::vector<int2> sts;
-    sts.reserve((size_t)H->n_super * (H->n_super + 1) / 2);
+    std::vector<int2> st_cached, st_gen, st_mixed;
     for (int r = 0; r < H->n_super; ++r)
-        for (int c = r; c < H->n_super; ++c) sts.push_back(make_int2(r, c));
+        for (int c = r; c < H->n_super; ++c) {
+            const int64_t n_lo = (int64_t)r * kSuper / block_size;
+            const int64_t n_hi = (std::min<int64_t>(D, (int64_t)(r + 1) * kSuper) - 1) / block_size;
+            const int64_t m_lo = (int64_t)c * kSuper / block_size;
+            const int64_t m_hi = (std::min<int64_t>(D, (int64_t)(c + 1) * kSuper) - 1) / block_size;
+            int64_t n_cached = 0, n_canon = 0;
+            for (int64_t n = n_lo; n <= n_hi; ++n)
+                for (int64_t m = std::max(m_lo, n); m <= m_hi; ++m) {
+                    ++n_canon;
+                    n_cached += slot[n * nb + m] >= 0;
+                }
+            const int2 t = make_int2(r, c);
+            if (n_cached == n_canon) st_cached.push_back(t);
+            else if (n_cached == 0) st_gen.push_back(t);
+            else st_mixed.push_back(t);
+        }
+    H->n_st_cached = (int64_t)st_cached.size();
+    H->n_st_gen = (int64_t)st_gen.size();
+    std::vector<int2> sts(st_cached);
+    sts.insert(sts.end(), st_gen.begin(), st_gen.end());
+    sts.insert(sts.end(), st_mixed.begin(), st_mixed.end());
     H->n_st = (int64_t)sts.size();
     HIP_TRY(hipMalloc((void**)&H->d_st, sts.size() * sizeof(int2)));
     HIP_TRY(hipMemcpy(H->d_st, sts.data(), sts.size() * sizeof(int2), hipMemcpyHostToDevice));
@@ -1157,7 +1209,7 @@ procmv_status procmv_set_tile_shape(procmv_op_t H, int32_t shape)
 {
     procmv_status st = check_op(H);
     if (st != PROCMV_OK) return st;
-    if (shape < 0 || shape > 2) return fail(PROCMV_ERR_INVALID_ARG, "tile shape %d", shape);
+    if (shape < -1 || shape > 2) return fail(PROCMV_ERR_INVALID_ARG, "tile shape %d", shape);
     H->tile_shape = shape;
     return PROCMV_OK;
 }
@@ -1183,7 +1235,7 @@ procmv_status procmv_autotune(procmv_op_t H, int32_t nvec, int32_t reps, void* s
     (void)hipEventCreate(&e1);
     double best = 1e30;
     int bshape = H->tile_shape;
-    for (int shape = 0; shape < 3 && st == PROCMV_OK; ++shape) {
+    for (int shape = -1; shape < 3 && st == PROCMV_OK; ++shape) {
         H->tile_shape = shape;
         st = procmv_apply(H, X, H->D, Y, H->D, nvec, stream);
         if (st != PROCMV_OK) break;

@@ -17,6 +17,8 @@
 // in a fixed order: no atomics, bit-reproducible results.
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace procmv {
@@ -76,6 +78,34 @@ __device__ __forceinline__ float wave_reduce_scatter(float (&v)[N])
 #pragma unroll
     for (int mask = 32 / N; mask >= 1; mask /= 2) r += __shfl_xor(r, mask);
     return r;
+}
+
+// One entry h = H_ij of a tile row applied both ways: dir += h x_j for the
+// row, tr += conj(h) x_i for the column (real entries for the sinc-DVR).  ok
+// masks entries outside the canonical triangle or the matrix, upper keeps the
+// diagonal out of the transposed sum.
+template <int NV, int GEN>
+__device__ __forceinline__ void apply_entry(float2 (&dir)[NV], float2 (&tr)[NV], float2 h,
+                                            bool ok, bool upper, const float2 (&xj)[NV],
+                                            const float2* xi)
+{
+    if (GEN == 0) {
+        if (!ok) h = make_float2(0.f, 0.f);
+        const float2 ht = upper ? h : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            cfma(dir[v], h, xj[v]);
+            cfma_conj(tr[v], ht, xi[v]);
+        }
+    } else {
+        const float hv = ok ? h.x : 0.f;
+        const float hvt = upper ? hv : 0.f;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            rfma(dir[v], hv, xj[v]);
+            rfma(tr[v], hvt, xi[v]);
+        }
+    }
 }
 
 // Block pair slot of the tile whose first row/column are (i0, j0).
@@ -268,6 +298,178 @@ __device__ __forceinline__ void super_tile(const TileArgs& a, int sr, int sc,
     }
 }
 
+// One super-tile of an operator whose canonical pairs are all cached: the
+// same arithmetic, in the same order, as super_tile with a cached source (so
+// the results are bit-identical), with the cache reads software-pipelined.
+// The tiles of the super-tile are walked row by row, SC per tile row; the
+// loads of tile t + PF (its RW entries per lane and the lane's x_j) are
+// issued before tile t is applied, into one of 2 PF register buffers indexed
+// by the tile column, and the x rows of the next tile row are fetched at the
+// start of the current one into a second LDS buffer.  Every memory wait is
+// then for data requested PF tiles earlier.  PF = 1 with three waves per SIMD
+// measured fastest on MI355X (more buffers cost occupancy).
+template <int NV, int RW, int GEN, int PF>
+__device__ __forceinline__ void super_tile_cached(const TileArgs& a, int sr, int sc,
+                                                  float2 (*red)[64][NV],
+                                                  float2 (*xs2)[4 * RW][NV])
+{
+    constexpr int TR = 4 * RW;
+    constexpr int SR = kSuper / TR;
+    constexpr int SC = kSuper / 64;
+    constexpr int NR = 2 * RW * NV;
+    constexpr int NB = 2 * PF;           // register buffers (tiles in flight + 1)
+    static_assert(SC % NB == 0, "buffer rotation");
+    using Entry = typename std::conditional<GEN == 0, float2, float>::type;
+
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const bool diag_st = (sr == sc);
+    const int row0 = sr * kSuper, col0 = sc * kSuper;
+    const int D = a.D;
+    const int bb = a.src.b;
+    const Entry* __restrict__ slots = (const Entry*)a.src.slots;
+    const int n_rows = min(SR, (D - row0 + TR - 1) / TR);   // tile rows inside D
+
+    float2 tr[SC][NV];
+#pragma unroll
+    for (int c = 0; c < SC; ++c)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) tr[c][v] = make_float2(0.f, 0.f);
+
+    Entry hb[NB][RW];
+    float2 xb[NB][NV];
+    // Issue the loads of tile (rr, cc) into buffer cc % NB.  Tiles that are not
+    // applied (past D, or below the diagonal) read the first entries of slot 0.
+    auto issue = [&](int rr, int cc) {
+        const int trow0 = row0 + rr * TR, tcol0 = col0 + cc * 64;
+        const bool live = tcol0 < D && !(diag_st && rr * TR > cc * 64 + 63);
+        size_t base = 0;
+        if (live) {
+            const int n0 = (trow0 / bb) * bb, m0 = (tcol0 / bb) * bb;
+            base = (size_t)tile_slot(a.src, trow0, tcol0) * bb * bb +
+                   (size_t)(trow0 + w * RW - n0) * bb + (tcol0 + lane - m0);
+        }
+        const Entry* sp = slots + base;
+#pragma unroll
+        for (int r = 0; r < RW; ++r) hb[cc % NB][r] = sp[(size_t)r * bb];
+        const int j = tcol0 + lane;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            xb[cc % NB][v] = (live && j < D) ? a.X[v * a.ldx + j] : make_float2(0.f, 0.f);
+    };
+    auto stage = [&](int rr) {             // x of the rows of tile row rr
+        const int q = threadIdx.x;
+        float2 x = make_float2(0.f, 0.f);
+        if (q < TR * NV) {
+            const int i = row0 + rr * TR + q / NV;
+            if (i < D) x = a.X[(q % NV) * a.ldx + i];
+        }
+        return x;
+    };
+
+    {
+        const float2 x0 = stage(0);
+        if (threadIdx.x < TR * NV) xs2[0][threadIdx.x / NV][threadIdx.x % NV] = x0;
+    }
+    if (n_rows > 0) {
+#pragma unroll
+        for (int c = 0; c < PF; ++c) issue(0, c);
+    }
+    __syncthreads();
+
+    for (int rr = 0; rr < n_rows; ++rr) {
+        const int trow0 = row0 + rr * TR;
+        const int ib = trow0 + w * RW;
+        const bool more = rr + 1 < n_rows;
+        const float2 xnext = more ? stage(rr + 1) : make_float2(0.f, 0.f);
+        const float2 (*xs)[NV] = xs2[rr & 1];
+        float2 dir[RW][NV];
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) dir[r][v] = make_float2(0.f, 0.f);
+
+#pragma unroll
+        for (int cc = 0; cc < SC; ++cc) {
+            // prefetch PF tiles ahead: (rr, cc + PF) or (rr + 1, cc + PF - SC)
+            if (cc + PF < SC) issue(rr, cc + PF);
+            else if (more) issue(rr + 1, cc + PF - SC);
+            const int tcol0 = col0 + cc * 64;
+            if (tcol0 >= D || (diag_st && rr * TR > cc * 64 + 63)) continue;
+            const int j = tcol0 + lane;
+            const bool jin = j < D;
+            float2 xj[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) xj[v] = xb[cc % NB][v];
+            // interior tiles (inside D, strictly above the diagonal) need no masks
+            const bool interior = tcol0 + 64 <= D && trow0 + TR <= D &&
+                                  (!diag_st || rr * TR + TR - 1 < cc * 64);
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                float2 h;
+                if (GEN == 0) h = *(const float2*)&hb[cc % NB][r];
+                else h = make_float2(*(const float*)&hb[cc % NB][r], 0.f);
+                if (interior) {
+                    apply_entry<NV, GEN>(dir[r], tr[cc], h, true, true, xj, xs[w * RW + r]);
+                } else {
+                    const int i = ib + r;
+                    const bool ok = jin && (i < D) && (i <= j);
+                    apply_entry<NV, GEN>(dir[r], tr[cc], h, ok, ok && (i < j), xj,
+                                         xs[w * RW + r]);
+                }
+            }
+        }
+
+        // direct partial of this tile row (as in super_tile)
+        float vals[NR];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                vals[(v * RW + r) * 2 + 0] = dir[r][v].x;
+                vals[(v * RW + r) * 2 + 1] = dir[r][v].y;
+            }
+        const float tot = wave_reduce_scatter<NR>(vals);
+        constexpr int G = 64 / NR;
+        if ((lane % G) == 0) {
+            const int idx = lane / G;
+            const int comp = idx & 1;
+            const int r = (idx >> 1) % RW;
+            const int v = (idx >> 1) / RW;
+            const int i = ib + r;
+            if (i < D) {
+                float* p = (float*)(a.P + ((size_t)sc * NV + v) * a.ldp + i);
+                p[comp] = tot;
+            }
+        }
+        if (more && threadIdx.x < TR * NV)
+            xs2[(rr + 1) & 1][threadIdx.x / NV][threadIdx.x % NV] = xnext;
+        __syncthreads();
+    }
+
+    const int slot_t = diag_st ? a.n_super : sr;
+#pragma unroll
+    for (int cc = 0; cc < SC; ++cc) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) red[w][lane][v] = tr[cc][v];
+        __syncthreads();
+        if (w == 0) {
+            const int j = col0 + cc * 64 + lane;
+            if (j < D) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    float2 s = red[0][lane][v];
+                    s.x += red[1][lane][v].x; s.y += red[1][lane][v].y;
+                    s.x += red[2][lane][v].x; s.y += red[2][lane][v].y;
+                    s.x += red[3][lane][v].x; s.y += red[3][lane][v].y;
+                    a.P[((size_t)slot_t * NV + v) * a.ldp + j] = s;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <int NV, int RW, int GEN, int SRC>
 __global__ __launch_bounds__(256) void tile_apply_kernel(TileArgs a)
 {
@@ -275,6 +477,17 @@ __global__ __launch_bounds__(256) void tile_apply_kernel(TileArgs a)
     __shared__ float2 xs[4 * RW][NV];
     const int2 st = a.st_list[blockIdx.x];
     super_tile<NV, RW, GEN, SRC>(a, st.x, st.y, red, xs);
+}
+
+// Single-vector products of a fully cached operator (tile shape 0), one tile
+// of prefetch.
+template <int RW, int GEN, int PF>
+__global__ __launch_bounds__(256, 3) void tile_apply_cached_kernel(TileArgs a)
+{
+    __shared__ float2 red[4][64][1];
+    __shared__ float2 xs[2][4 * RW][1];
+    const int2 st = a.st_list[blockIdx.x];
+    super_tile_cached<1, RW, GEN, PF>(a, st.x, st.y, red, xs);
 }
 
 // Batched persistent form: every workgroup walks the flattened list of
@@ -385,6 +598,16 @@ hipError_t launch_nv(const TileArgs& a, int n_st, hipStream_t s)
 {
     const bool cached = a.src.pair_slot != nullptr;
     const dim3 g(n_st), b(256);
+    if constexpr (NV == 1 && RW == 8) {
+        // single vector, fully cached, default tile shape: pipelined reads
+        if (cached && a.src.all_cached) {
+            if (a.src.gen == 0)
+                hipLaunchKernelGGL((tile_apply_cached_kernel<RW, 0, 1>), g, b, 0, s, a);
+            else
+                hipLaunchKernelGGL((tile_apply_cached_kernel<RW, 1, 1>), g, b, 0, s, a);
+            return hipGetLastError();
+        }
+    }
     if (a.src.gen == 0) {
         if (cached) hipLaunchKernelGGL((tile_apply_kernel<NV, RW, 0, 1>), g, b, 0, s, a);
         else hipLaunchKernelGGL((tile_apply_kernel<NV, RW, 0, 0>), g, b, 0, s, a);

@@ -25,6 +25,7 @@ struct SourceArgs {
     const void* slots;         // slot pool: b*b complex64 (GUE) or float (DVR) per slot
     int32_t b;
     int32_t n_blk;
+    int32_t all_cached;        // every canonical pair has a slot
 };
 
 struct TileArgs {

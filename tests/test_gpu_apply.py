@@ -82,21 +82,25 @@ def test_gue_ragged_and_multivector(pm, orc, D, nvec, b):
 
 
 @pytest.mark.parametrize("gen", ["gue", "dvr"])
-def test_storage_modes_agree(pm, orc, gen):
+@pytest.mark.parametrize("nvec,shape", [(4, 1), (1, 0)])
+def test_storage_modes_agree(pm, orc, gen, nvec, shape):
     """Every storage mode gives the same product.  Cached modes read the very
-    entries the generator emits, through the same two-sided tile kernel, so
-    with one tile shape they are bit-identical to each other for every block
-    size, and for GUE also to the procedural mode.  The procedural sinc-DVR mode runs the Toeplitz
+    entries the generator emits, with the same arithmetic in the same order,
+    so with one tile shape they are bit-identical to each other for every
+    block size, and for GUE also to the procedural mode.  One vector at shape
+    0 covers the pipelined kernel of fully cached super-tiles (full cache, and
+    the cached super-tiles of a partial cache at b = 512) against the mixed
+    super-tiles of b = 128.  The procedural sinc-DVR mode runs the Toeplitz
     kernel (different summation order): equal within binary32 rounding."""
     D = 1500
-    Xh = workloads.gaussian_vectors(D, 4, seed=3)
+    Xh = workloads.gaussian_vectors(D, nvec, seed=3)
     X = to_dev(Xh)
     outs = {}
     for strat, f in [(pm.PROCEDURAL, 0.0), (pm.PARTIAL, 0.5), (pm.PARTIAL, 0.25),
                      (pm.FULL, 1.0)]:
         for b in (128, 512):
             op = pm.Operator.gue(D, seed=4) if gen == "gue" else pm.Operator.dvr(D)
-            op.plan(b, strat, f).set_tile_shape(1)
+            op.plan(b, strat, f).set_tile_shape(shape)
             info = op.plan_info()
             if strat == pm.FULL:
                 assert info["p_cache"] == info["n_pair"]
@@ -114,6 +118,23 @@ def test_storage_modes_agree(pm, orc, gen):
         assert np.array_equal(procs[0], cached[0])
     for o in (procs[0], cached[0]):
         assert rel_l2(o, ref) <= TOL_FP32
+
+
+@pytest.mark.parametrize("gen", ["gue", "dvr"])
+def test_default_shapes_partial_cache(pm, orc, gen):
+    """Default tile shapes (one launch per super-tile class: cached, generated,
+    mixed) on partial caches at both sides of the super-tile edge, against the
+    binary64 oracle, at a size with several super-tiles and a ragged tail."""
+    D = 2000
+    Xh = workloads.gaussian_vectors(D, 2, seed=5)
+    ref = orc.gue_apply_rows(6, D, Xh) if gen == "gue" else orc.DVR(D).apply_rows(Xh)
+    for b, f in [(128, 0.5), (256, 0.25), (512, 0.75), (1024, 0.5)]:
+        for nv in (1, 2):
+            op = pm.Operator.gue(D, seed=6) if gen == "gue" else pm.Operator.dvr(D)
+            op.plan(b, pm.PARTIAL, f)
+            got = to_host(op.apply(to_dev(Xh[:nv])))
+            assert rel_l2(got, ref[:nv]) <= TOL_FP32, (b, f, nv)
+            op.close()
 
 
 @pytest.mark.parametrize("D,nvec", [(2, 1), (63, 2), (3001, 3), (8192, 2),
