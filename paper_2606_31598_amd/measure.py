@@ -1,0 +1,158 @@
+"""Timings of the product on the paper's configurations (one MI355X).
+
+    python -m paper_2606_31598_amd.measure c0|c2|c3 [--reps N]
+
+Each sub-command prints JSON lines with the measured quantities of one
+configuration; accuracy against the binary64 reference lives in the tests.
+
+* c0 -- Philox-GUE D = 2048, b = 256, procedural, one vector: ten repeated
+  products (paper Sec. V, small dense case).
+* c2 -- 256 uneven Philox-GUE instances (D uniform in [512, 8192], seeds
+  1..256), four vectors: one persistent batched launch (autotuned) against
+  one product per instance, and batched Chebyshev steps replayed from a HIP
+  graph against per-instance steps.
+* c3 -- Philox-GUE D = 262144, 16 vectors, b = 512: procedural and 25%
+  canonical cache, binary32 and split-bfloat16 matrix-core products; cache
+  fill time and the bandwidth of the cached part.
+"""
+import argparse
+import json
+import time
+
+import numpy as np
+
+
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    return torch
+
+
+def _emit(rec):
+    print(json.dumps(rec), flush=True)
+
+
+def _time(fn, reps, torch):
+    """Mean seconds per call over `reps` calls (HIP events, after one warm call)."""
+    fn()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def c0(reps):
+    torch = _cuda()
+    from . import procmv as pm, workloads
+    D = 2048
+    op = pm.Operator.gue(D, seed=1).plan(256, pm.PROCEDURAL)
+    X = torch.from_numpy(workloads.gaussian_vectors(D, 1, seed=2).astype(np.complex64)).cuda()
+    Y = torch.empty_like(X)
+    t = _time(lambda: op.apply(X, Y), max(reps, 10), torch)
+    shape, tuned = op.autotune(1, reps=max(reps, 10))
+    t_tuned = _time(lambda: op.apply(X, Y), max(reps, 10), torch)
+    _emit({"config": "c0", "workload": "Philox-GUE D=2048 b=256 procedural, 1 vector",
+           "us_per_product": t * 1e6, "gelem_s": D * D / t / 1e9,
+           "autotuned_shape": shape, "us_per_product_autotuned": t_tuned * 1e6,
+           "gelem_s_autotuned": D * D / t_tuned / 1e9})
+
+
+def c2(reps):
+    torch = _cuda()
+    from . import procmv as pm, workloads
+    sizes = workloads.batch_sizes(256)
+    nvec = 4
+    ops = [pm.Operator.gue(int(D), seed=k + 1).plan(256) for k, D in enumerate(sizes)]
+    B = pm.Batch(ops, nvec)
+    parts = [workloads.gaussian_vectors(int(D), nvec, seed=100 + k).ravel()
+             for k, D in enumerate(sizes)]
+    X = torch.from_numpy(np.concatenate(parts).astype(np.complex64)).cuda()
+    Y = torch.empty_like(X)
+    elems = float(np.sum(sizes.astype(np.float64) ** 2))
+    tuned_ms = B.autotune(X, Y, reps=2)
+    t_batch = _time(lambda: B.apply(X, Y), reps, torch)
+    views = [(X[int(o):int(o) + nvec * int(D)].view(nvec, int(D)),
+              Y[int(o):int(o) + nvec * int(D)].view(nvec, int(D)))
+             for o, D in zip(B.offsets, sizes)]
+
+    def per_instance():
+        for op, (xv, yv) in zip(ops, views):
+            op.apply(xv, yv)
+    t_each = _time(per_instance, max(1, reps // 4), torch)
+    _emit({"config": "c2", "workload": "256 Philox-GUE instances, D in [512, 8192], 4 vectors",
+           "sum_D2": elems, "batched_ms_per_product": t_batch * 1e3,
+           "batched_gelem_s": elems / t_batch / 1e9,
+           "batched_gelem_s_x4": nvec * elems / t_batch / 1e9,
+           "per_instance_ms_per_product": t_each * 1e3,
+           "per_instance_gelem_s": elems / t_each / 1e9,
+           "speedup": t_each / t_batch, "autotune_ms": tuned_ms, "batch_config": B.info()})
+    # Chebyshev steps (dt = 0.05, spectral interval c = 0, R = 2.5)
+    dt, c, R = 0.05, 0.0, 2.5
+    K = pm.cheb_order(R * dt, 1e-10)
+    psi = X.clone()
+    nsteps = 20
+    B.propagate(psi, dt, 1, c, R, graph=True)      # capture + first replay
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.propagate(psi, dt, nsteps, c, R, graph=True)
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / nsteps
+    t0 = time.perf_counter()
+    B.propagate(psi, dt, 2, c, R, graph=False)
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / 2
+    psis = [p.clone() for p, _ in views]
+    t0 = time.perf_counter()
+    for op, p in zip(ops, psis):
+        op.propagate(p, dt, nsteps=1, K=K, c=c, R=R)
+    torch.cuda.synchronize()
+    t_inst = time.perf_counter() - t0
+    _emit({"config": "c2", "chebyshev_K": K,
+           "batched_graph_steps_per_s": 1.0 / t_graph,
+           "batched_eager_steps_per_s": 1.0 / t_eager,
+           "per_instance_steps_per_s": 1.0 / t_inst,
+           "graph_gelem_s": (K + 1) * elems / t_graph / 1e9})
+
+
+def c3(reps):
+    torch = _cuda()
+    from . import procmv as pm, workloads
+    D, nvec, b = 262144, 16, 512
+    X = torch.from_numpy(workloads.gaussian_vectors(D, nvec, seed=2).astype(np.complex64)).cuda()
+    Y = torch.empty_like(X)
+    for strat, f in ((pm.PROCEDURAL, 0.0), (pm.PARTIAL, 0.25)):
+        for prec, pname in ((pm.FP32, "fp32"), (pm.SPLIT_BF16, "split_bf16")):
+            op = pm.Operator.gue(D, seed=1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            op.plan(b, strat, f, precision=prec)
+            torch.cuda.synchronize()
+            t_plan = time.perf_counter() - t0
+            info = op.plan_info()
+            t = _time(lambda: op.apply(X, Y), reps, torch)
+            rec = {"config": "c3", "workload": f"Philox-GUE D={D}, {nvec} vectors, b={b}",
+                   "strategy": "procedural" if f == 0 else f"partial {f}", "precision": pname,
+                   "plan_s": t_plan, "cache_gb": info["cache_bytes"] / 1e9,
+                   "ms_per_product": t * 1e3, "gelem_s": D * D / t / 1e9,
+                   "gelem_s_x16": nvec * D * D / t / 1e9}
+            _emit(rec)
+            op.close()
+            torch.cuda.synchronize()
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["c0", "c2", "c3"])
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args(argv)
+    {"c0": c0, "c2": c2, "c3": c3}[args.cmd](args.reps)
+
+
+if __name__ == "__main__":
+    main()
