@@ -180,8 +180,10 @@ procmv_status procmv_autotune(procmv_op_t H, int32_t nvec, int32_t reps,
  * vector block) explicitly, or -1 for the default that procmv_plan sets: the
  * super-tiles whose canonical pairs are all cached use shape 0 (narrow tiles
  * streaming the cache), those with none cached shape 2 for the Philox-GUE
- * generator (wide tiles) and 0 for the sinc-DVR one, mixed ones (block size
- * below 256) shape 0, one launch per class.  With one explicit shape, products are bit-identical across storage
+ * generator on 256-wide super-tiles (wide tiles) and 0 otherwise, mixed ones (block size
+ * below the super-tile edge) shape 0, one launch per class.  Shapes whose
+ * tile rows exceed the super-tile edge (64 entries for D <= 5632, 128 for
+ * D <= 11264, else 256) are reduced to the largest that fits.  With one explicit shape, products are bit-identical across storage
  * modes and block sizes. */
 procmv_status procmv_set_tile_shape(procmv_op_t H, int32_t shape);
 

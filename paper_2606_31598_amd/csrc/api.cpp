@@ -71,6 +71,7 @@ struct procmv_op {
     int32_t* d_pair_slot = nullptr;
     void* d_slots = nullptr;
     int2* d_pairs = nullptr;
+    int32_t se = 4;             // super-tile edge in 64-column tiles
     int32_t n_super = 0;
     int64_t n_st = 0;
     int2* d_st = nullptr;       // cached super-tiles, then generated, then mixed
@@ -260,8 +261,6 @@ struct TileOut {
     const float* vdiag = nullptr;
 };
 
-static_assert(kSuperM == kSuper, "the MFMA and VALU tile kernels share one super-tile list");
-
 // Whether a block of `remaining` vectors goes to the matrix cores: always in
 // split-bf16 precision, and in binary32 once there are enough vectors for the
 // per-tile product to be a contraction worth a GEMM.
@@ -311,6 +310,7 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
         TileArgs a{};
         a.src = op->source();
         a.D = (int32_t)op->D;
+        a.se = op->se;
         a.n_super = op->n_super;
         a.nv = nv;
         a.st_list = op->d_st;
@@ -324,7 +324,8 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
         } else {
             // one launch per super-tile class; the default shape streams the
             // cache with narrow tiles and generates Philox entries with wide
-            // ones (sinc-DVR entries are table reads: narrow tiles)
+            // ones on the largest super-tiles (sinc-DVR entries are table
+            // reads, and small super-tiles have few rows: narrow tiles)
             const int64_t n_c = op->n_st_cached, n_g = op->n_st_gen;
             const int64_t n_m = op->n_st - n_c - n_g;
             const SourceArgs src = a.src;
@@ -338,7 +339,7 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
                 a.src.pair_slot = nullptr;
                 a.src.all_cached = 0;
                 a.st_list = op->d_st + n_c;
-                const int gshape = op->gen == 0 ? 2 : 0;
+                const int gshape = (op->gen == 0 && op->se == kSuper / 64) ? 2 : 0;
                 HIP_TRY(launch_tile_apply(a, nv, op->tile_shape >= 0 ? op->tile_shape : gshape,
                                           (int)n_g, s));
             }
@@ -493,14 +494,16 @@ procmv_status procmv_plan(procmv_op_t H, int32_t block_size,
     H->tile_shape = -1;
     // super-tile list, grouped by how its canonical pairs are stored: all
     // cached, none cached, or mixed (only when b < the super-tile edge)
-    H->n_super = (int32_t)((D + kSuper - 1) / kSuper);
+    H->se = super_edge_tiles(D);
+    const int64_t E = 64 * H->se;
+    H->n_super = (int32_t)((D + E - 1) / E);
     std::vector<int2> st_cached, st_gen, st_mixed;
     for (int r = 0; r < H->n_super; ++r)
         for (int c = r; c < H->n_super; ++c) {
-            const int64_t n_lo = (int64_t)r * kSuper / block_size;
-            const int64_t n_hi = (std::min<int64_t>(D, (int64_t)(r + 1) * kSuper) - 1) / block_size;
-            const int64_t m_lo = (int64_t)c * kSuper / block_size;
-            const int64_t m_hi = (std::min<int64_t>(D, (int64_t)(c + 1) * kSuper) - 1) / block_size;
+            const int64_t n_lo = (int64_t)r * E / block_size;
+            const int64_t n_hi = (std::min<int64_t>(D, (int64_t)(r + 1) * E) - 1) / block_size;
+            const int64_t m_lo = (int64_t)c * E / block_size;
+            const int64_t m_hi = (std::min<int64_t>(D, (int64_t)(c + 1) * E) - 1) / block_size;
             int64_t n_cached = 0, n_canon = 0;
             for (int64_t n = n_lo; n <= n_hi; ++n)
                 for (int64_t m = std::max(m_lo, n); m <= m_hi; ++m) {
@@ -880,6 +883,7 @@ procmv_status batch_tiles(procmv_batch* B, const float2* xbase, hipStream_t s)
     L.shape = B->shape;
     L.grid = (int)std::min<int64_t>(B->grid, B->n_items);
     L.cached = 0;
+    L.min_se = kSuper / 64;
     for (procmv_op* op : B->ops) L.cached |= (op->p_cache > 0) ? 1 : 0;
     HIP_TRY(launch_tile_apply_batched(L, s));
     return PROCMV_OK;
@@ -939,7 +943,10 @@ procmv_status procmv_batch_create(const procmv_op_t* ops, int32_t n, int32_t nve
         B->off[k] = B->total;
         B->total += (int64_t)nvec * ops[k]->D;
         pstart[k] = poff;
-        poff += (int64_t)(ops[k]->n_super + 1) * nvec * ops[k]->D;
+        // batches take the largest super-tile edge for every instance: the
+        // instances already fill the device, and big super-tiles carry less
+        // per-item overhead
+        poff += ((ops[k]->D + kSuper - 1) / kSuper + 1) * nvec * ops[k]->D;
     }
     hipError_t e = hipMalloc((void**)&B->d_P, (size_t)poff * sizeof(float2));
     if (e != hipSuccess) {
@@ -955,18 +962,19 @@ procmv_status procmv_batch_create(const procmv_op_t* ops, int32_t n, int32_t nve
         a = TileArgs{};
         a.src = op->source();
         a.D = (int32_t)op->D;
-        a.n_super = op->n_super;
+        a.se = kSuper / 64;
+        a.n_super = (int32_t)((op->D + kSuper - 1) / kSuper);
         a.nv = nvec;
         a.ldx = op->D;
         a.xoff = B->off[k];
         a.P = B->d_P + pstart[k];
         a.ldp = op->D;
-        for (int r = 0; r < op->n_super; ++r)
-            for (int c = r; c < op->n_super; ++c) B->per_inst[k].push_back(make_int4(k, r, c, 0));
+        for (int r = 0; r < a.n_super; ++r)
+            for (int c = r; c < a.n_super; ++c) B->per_inst[k].push_back(make_int4(k, r, c, 0));
         B->n_items += (int64_t)B->per_inst[k].size();
         ri[k] = BatchReduceItem{};
         ri[k].D = (int32_t)op->D;
-        ri[k].n_slots = op->n_super + 1;
+        ri[k].n_slots = a.n_super + 1;
         ri[k].off = B->off[k];
         ri[k].P = a.P;
         ri[k].ldp = op->D;
@@ -1127,7 +1135,7 @@ procmv_status procmv_batch_propagate(procmv_batch_t B, void* psi, double dt, int
             procmv_op* op = B->ops[k];
             ci[k] = BatchReduceItem{};
             ci[k].D = (int32_t)op->D;
-            ci[k].n_slots = op->n_super + 1;
+            ci[k].n_slots = B->targs[k].n_super + 1;
             ci[k].off = B->off[k];
             ci[k].P = B->targs[k].P;
             ci[k].ldp = op->D;
@@ -1466,7 +1474,7 @@ void plan_memory(int64_t D, int32_t nvec, int family, int32_t b, int32_t strateg
     else if (strategy == PROCMV_PARTIAL) p = (int64_t)std::floor(f * (double)npair);
     const double be = family == 0 ? 8.0 : 4.0;
     m_op = (double)p * b * b * be;
-    const int64_t ns = (D + kSuper - 1) / kSuper;
+    const int64_t ns = (D + 64 * super_edge_tiles(D) - 1) / (64 * super_edge_tiles(D));
     const int chunk = nvec >= 8 ? 16 : nvec >= 4 ? 4 : nvec >= 2 ? 2 : 1;
     const double slots = (family == 1 && strategy == PROCMV_PROCEDURAL && nvec < 8)
                              ? (double)((D + 511) / 512) : (double)(ns + 1);

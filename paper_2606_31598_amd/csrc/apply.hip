@@ -6,14 +6,15 @@
 // obtained once and applied twice: y_i += H_ij x_j and y_j += conj(H_ij) x_i.
 //
 // Work decomposition.  The canonical upper triangle is cut into square
-// super-tiles of kSuper x kSuper; one workgroup (4 waves of 64) owns one
+// super-tiles of E x E (E = 64, 128 or 256 by dimension, see
+// super_edge_tiles); one workgroup (4 waves of 64) owns one
 // super-tile and walks its tiles of TR x 64 entries, TR = 4 * RW, each wave
 // taking RW consecutive rows and each lane one column.  Direct sums for the
 // wave's rows stay in registers across the super-tile row and are reduced
 // across lanes once; transposed sums for each lane's columns stay in
 // registers across the whole super-tile and are reduced across waves once.
 // Both go to a partial buffer in which every output element has exactly one
-// slot per super-tile band (see kSuper), and a second kernel sums the slots
+// slot per super-tile band (see kernels.h), and a second kernel sums the slots
 // in a fixed order: no atomics, bit-reproducible results.
 #include <hip/hip_ext.h>
 
@@ -123,15 +124,16 @@ __device__ __forceinline__ void super_tile(const TileArgs& a, int sr, int sc,
                                            float2 (*red)[64][NV], float2 (*xs)[NV])
 {
     constexpr int TR = 4 * RW;          // rows per tile
-    constexpr int SR = kSuper / TR;     // row tiles per super-tile
-    constexpr int SC = kSuper / 64;     // column tiles per super-tile
+    constexpr int SC = kSuper / 64;     // most column tiles per super-tile
     constexpr int NR = 2 * RW * NV;     // direct values reduced across lanes
     static_assert(NR == 16 || NR == 32 || NR == 64, "tile shape");
+    const int sct = a.se;               // column tiles per super-tile here
+    const int SR = 64 * sct / TR;       // tile rows (the launcher keeps TR <= edge)
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const bool diag_st = (sr == sc);
-    const int row0 = sr * kSuper, col0 = sc * kSuper;
+    const int row0 = sr * 64 * sct, col0 = sc * 64 * sct;
     const int D = a.D;
 
     float2 tr[SC][NV];
@@ -159,6 +161,7 @@ __device__ __forceinline__ void super_tile(const TileArgs& a, int sr, int sc,
 
 #pragma unroll
         for (int cc = 0; cc < SC; ++cc) {
+            if (cc >= sct) break;
             const int tcol0 = col0 + cc * 64;
             if (trow0 >= D || tcol0 >= D) continue;
             // tiles strictly below the diagonal belong to the transpose
@@ -278,6 +281,7 @@ __device__ __forceinline__ void super_tile(const TileArgs& a, int sr, int sc,
     const int slot_t = diag_st ? a.n_super : sr;
 #pragma unroll
     for (int cc = 0; cc < SC; ++cc) {
+        if (cc >= sct) break;
 #pragma unroll
         for (int v = 0; v < NV; ++v) red[w][lane][v] = tr[cc][v];
         __syncthreads();
@@ -314,17 +318,18 @@ __device__ __forceinline__ void super_tile_cached(const TileArgs& a, int sr, int
                                                   float2 (*xs2)[4 * RW][NV])
 {
     constexpr int TR = 4 * RW;
-    constexpr int SR = kSuper / TR;
     constexpr int SC = kSuper / 64;
     constexpr int NR = 2 * RW * NV;
     constexpr int NB = 2 * PF;           // register buffers (tiles in flight + 1)
     static_assert(SC % NB == 0, "buffer rotation");
+    const int sct = a.se;                // column tiles per super-tile: a multiple
+    const int SR = 64 * sct / TR;        // of NB (the launcher checks), TR <= edge
     using Entry = typename std::conditional<GEN == 0, float2, float>::type;
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const bool diag_st = (sr == sc);
-    const int row0 = sr * kSuper, col0 = sc * kSuper;
+    const int row0 = sr * 64 * sct, col0 = sc * 64 * sct;
     const int D = a.D;
     const int bb = a.src.b;
     const Entry* __restrict__ slots = (const Entry*)a.src.slots;
@@ -391,9 +396,10 @@ __device__ __forceinline__ void super_tile_cached(const TileArgs& a, int sr, int
 
 #pragma unroll
         for (int cc = 0; cc < SC; ++cc) {
-            // prefetch PF tiles ahead: (rr, cc + PF) or (rr + 1, cc + PF - SC)
-            if (cc + PF < SC) issue(rr, cc + PF);
-            else if (more) issue(rr + 1, cc + PF - SC);
+            if (cc >= sct) break;
+            // prefetch PF tiles ahead: (rr, cc + PF) or (rr + 1, cc + PF - sct)
+            if (cc + PF < sct) issue(rr, cc + PF);
+            else if (more) issue(rr + 1, cc + PF - sct);
             const int tcol0 = col0 + cc * 64;
             if (tcol0 >= D || (diag_st && rr * TR > cc * 64 + 63)) continue;
             const int j = tcol0 + lane;
@@ -450,6 +456,7 @@ __device__ __forceinline__ void super_tile_cached(const TileArgs& a, int sr, int
     const int slot_t = diag_st ? a.n_super : sr;
 #pragma unroll
     for (int cc = 0; cc < SC; ++cc) {
+        if (cc >= sct) break;
 #pragma unroll
         for (int v = 0; v < NV; ++v) red[w][lane][v] = tr[cc][v];
         __syncthreads();
@@ -599,8 +606,8 @@ hipError_t launch_nv(const TileArgs& a, int n_st, hipStream_t s)
     const bool cached = a.src.pair_slot != nullptr;
     const dim3 g(n_st), b(256);
     if constexpr (NV == 1 && RW == 8) {
-        // single vector, fully cached, default tile shape: pipelined reads
-        if (cached && a.src.all_cached) {
+        // single vector, fully cached, tile shape 0, even edge: pipelined reads
+        if (cached && a.src.all_cached && a.se % 2 == 0) {
             if (a.src.gen == 0)
                 hipLaunchKernelGGL((tile_apply_cached_kernel<RW, 0, 1>), g, b, 0, s, a);
             else
@@ -642,9 +649,17 @@ hipError_t launch_nv_batched(const BatchTileLaunch& b, hipStream_t s)
 
 }  // namespace
 
+// Largest tile shape <= shape whose tile rows (4 RW) fit the super-tile edge.
+static int fit_shape(int nv, int shape, int se)
+{
+    while (shape > 0 && 4 * (16 << shape) / (2 * nv) > 64 * se) --shape;
+    return shape;
+}
+
 // Tile shapes: rows per wave RW = (8, 16, 32) / (2 NV) for shape 0, 1, 2.
 hipError_t launch_tile_apply(const TileArgs& a, int nv, int shape, int n_st, hipStream_t s)
 {
+    shape = fit_shape(nv, shape, a.se);
 #define PROCMV_SHAPES(NV, R0, R1, R2)                                  \
     if (shape == 0) return launch_nv<NV, R0>(a, n_st, s);              \
     if (shape == 1) return launch_nv<NV, R1>(a, n_st, s);              \
@@ -660,8 +675,10 @@ hipError_t launch_tile_apply(const TileArgs& a, int nv, int shape, int n_st, hip
 #undef PROCMV_SHAPES
 }
 
-hipError_t launch_tile_apply_batched(const BatchTileLaunch& b, hipStream_t s)
+hipError_t launch_tile_apply_batched(const BatchTileLaunch& b0, hipStream_t s)
 {
+    BatchTileLaunch b = b0;
+    b.shape = fit_shape(b.nv, b.shape, b.min_se);
 #define PROCMV_SHAPES(NV, R0, R1, R2)                                  \
     if (b.shape == 0) return launch_nv_batched<NV, R0>(b, s);          \
     if (b.shape == 1) return launch_nv_batched<NV, R1>(b, s);          \

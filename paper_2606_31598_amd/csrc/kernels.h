@@ -7,14 +7,23 @@
 
 namespace procmv {
 
-// Square super-tile edge of the VALU tile kernel.  Output element i of band
-// B = i / kSuper receives exactly one partial per slot k in [0, N_s]:
+// Square super-tiles of E = 64 se entries (se = 1, 2 or 4 column tiles of 64)
+// are the work units of the tile kernels (VALU and MFMA).  Output element i
+// of band B = i / E receives exactly one partial per slot k in [0, N_s]:
 // slot k >= B from the direct product of super-tile (B, k), slot k < B from
 // the transposed product of super-tile (k, B), slot N_s from the transposed
 // product of the diagonal super-tile (B, B).
-constexpr int kSuper = 256;
-// Super-tile edge of the MFMA multi-vector kernel (same slot scheme).
-constexpr int kSuperM = 256;
+constexpr int kSuper = 256;   // largest edge (se = 4)
+
+// Edge in 64-column tiles for dimension D: the largest edge that still gives
+// at least 45 super-tile bands (about 1000 super-tiles, four per compute
+// unit), 64 below that.
+inline int super_edge_tiles(int64_t D)
+{
+    for (int se = 4; se > 1; se /= 2)
+        if ((D + 64 * se - 1) / (64 * se) >= 45) return se;
+    return 1;
+}
 
 // Where the entries of one tile come from.
 struct SourceArgs {
@@ -31,7 +40,8 @@ struct SourceArgs {
 struct TileArgs {
     SourceArgs src;
     int32_t D;
-    int32_t n_super;          // N_s = ceil(D / super-tile edge)
+    int32_t se;               // super-tile edge in 64-column tiles (1, 2, 4)
+    int32_t n_super;          // N_s = ceil(D / (64 se))
     int32_t nv;               // vectors in this launch (MFMA kernel: <= 16)
     const int2* st_list;      // super-tile coordinates (sr, sc), sr <= sc
     const float2* X;          // nvec-chunk base, vector v at X + v * ldx
@@ -49,6 +59,7 @@ struct BatchTileLaunch {
     const float2* xbase;      // packed vectors of all instances
     int gen, nv, shape, grid;
     int cached;               // some instance has cached block pairs
+    int min_se;               // smallest super-tile edge (64-column tiles) of the instances
 };
 
 // Sinc-DVR Toeplitz product: row bands x column chunks, one partial slot per

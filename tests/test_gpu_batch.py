@@ -1,9 +1,12 @@
 """GPU parity of batched products and batched Chebyshev propagation.
 
-A batch of independent operators goes through one persistent launch; its
-products must be bit-identical to the per-instance products (same kernels,
-same fixed reduction order), the captured HIP graph must reproduce the eager
-step on every replay, and sampled instances must match the binary64 oracle.
+A batch of independent operators goes through one persistent launch over
+super-tiles of edge 256 for every instance.  Its products must not depend on
+the persistent grid or the item order (same kernels, fixed reduction order:
+bit-identical), must equal the per-instance product bit for bit where the
+instance's own plan uses the same super-tile edge (D > 11264) and within
+binary32 rounding elsewhere, the captured HIP graph must reproduce the eager
+step on every replay, and every instance must match the binary64 oracle.
 """
 import numpy as np
 import pytest
@@ -42,25 +45,33 @@ def _unpack(buf, sizes, nvec):
 @pytest.mark.parametrize("nvec", [1, 4])
 def test_batched_apply_equals_per_instance(pm, orc, nvec):
     import torch
-    sizes = [700, 64, 1500, 257, 1024, 3, 999, 512]
+    sizes = [700, 64, 1500, 257, 1024, 3, 999, 11520]
     ops = [pm.Operator.gue(D, seed=10 + k).plan(256) for k, D in enumerate(sizes)]
     B = pm.Batch(ops, nvec)
     Xh = _packed(sizes, nvec, seed=1)
     X = torch.from_numpy(Xh.astype(np.complex64)).cuda()
     Y = torch.empty_like(X)
-    for cfg in [(2, 1024, 0), (0, 256, 1), (1, 2048, 0)]:
+    Xs = _unpack(Xh, sizes, nvec)
+    refs = [orc.gue_apply_rows(10 + k, D, Xs[k]) for k, D in enumerate(sizes)]
+    singles = []
+    for k, (op, D) in enumerate(zip(ops, sizes)):
+        Xk = X[int(B.offsets[k]):int(B.offsets[k]) + nvec * D].view(nvec, D)
+        singles.append(op.apply(Xk).cpu().numpy())
+    outs = {}
+    for cfg in [(2, 1024, 0), (2, 256, 1), (0, 256, 1), (1, 2048, 0)]:
         B.configure(*cfg)
         B.apply(X, Y)
         got = _unpack(Y.cpu().numpy(), sizes, nvec)
-        for k, (op, D) in enumerate(zip(ops, sizes)):
-            if cfg[0] != 2:          # procedural operators default to tile shape 2
-                continue
-            Xk = X[int(B.offsets[k]):int(B.offsets[k]) + nvec * D].view(nvec, D)
-            yk = op.apply(Xk).cpu().numpy()
-            assert np.array_equal(got[k], yk)
+        outs[cfg] = got
         for k, D in enumerate(sizes):
-            ref = orc.gue_apply_rows(10 + k, D, _unpack(Xh, sizes, nvec)[k])
-            assert rel_l2(got[k], ref) <= 1e-5
+            assert rel_l2(got[k], refs[k]) <= 1e-5, (cfg, D)
+            assert rel_l2(got[k], singles[k]) <= 1e-5, (cfg, D)
+        if cfg[0] == 2:
+            # procedural operators default to tile shape 2; D = 11520 plans
+            # the batch's super-tile edge too
+            assert np.array_equal(got[-1], singles[-1])
+    for a, b in zip(outs[(2, 1024, 0)], outs[(2, 256, 1)]):
+        assert np.array_equal(a, b)
 
 
 def test_batched_propagation_graph_replays(pm, orc):
@@ -80,12 +91,13 @@ def test_batched_propagation_graph_replays(pm, orc):
         torch.cuda.synchronize()
         assert torch.equal(eager, graph), f"replay {rep} differs from the eager step"
         assert np.max(np.abs(nrm - 1.0)) < 1e-5
-    # per-instance propagation gives the same bits
+    # per-instance propagation agrees within binary32 rounding (its plan uses
+    # a smaller super-tile edge at these sizes)
     for k, (op, D) in enumerate(zip(ops, sizes)):
         single = torch.from_numpy(_unpack(p0, sizes, nvec)[k].copy()).cuda()
         op.propagate(single, dt, nsteps=3, c=c, R=R)
         got = graph[int(B.offsets[k]):int(B.offsets[k]) + nvec * D].view(nvec, D)
-        assert torch.equal(single, got)
+        assert rel_l2(got.cpu().numpy(), single.cpu().numpy()) <= 1e-5
     # oracle on two instances
     for k in (0, 2):
         H = orc.gue_dense(20 + k, sizes[k])
