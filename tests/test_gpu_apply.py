@@ -176,3 +176,11 @@ def test_errors_reported(pm):
     with pytest.raises(pm.ProcmvError) as e:
         op.plan(64, pm.FULL, precision=7)
     assert e.value.status == 1
+    # empty vector sets and empty batches are argument errors, caught on the host
+    import ctypes
+    L = pm.load()
+    Y = torch.zeros_like(X)
+    p = ctypes.c_void_p
+    assert L.procmv_apply(op._h, p(X.data_ptr()), 512, p(Y.data_ptr()), 512, 0, None) == 1
+    h = ctypes.c_void_p()
+    assert L.procmv_batch_create((ctypes.c_void_p * 1)(), 0, 1, ctypes.byref(h)) == 1
