@@ -161,7 +161,7 @@ __device__ __forceinline__ void super_tile(const TileArgs& a, int sr, int sc,
 
 #pragma unroll
         for (int cc = 0; cc < SC; ++cc) {
-            if (cc >= sct) break;
+            if (cc >= sct) continue;
             const int tcol0 = col0 + cc * 64;
             if (trow0 >= D || tcol0 >= D) continue;
             // tiles strictly below the diagonal belong to the transpose
@@ -281,7 +281,7 @@ __device__ __forceinline__ void super_tile(const TileArgs& a, int sr, int sc,
     const int slot_t = diag_st ? a.n_super : sr;
 #pragma unroll
     for (int cc = 0; cc < SC; ++cc) {
-        if (cc >= sct) break;
+        if (cc >= sct) continue;
 #pragma unroll
         for (int v = 0; v < NV; ++v) red[w][lane][v] = tr[cc][v];
         __syncthreads();
@@ -322,8 +322,8 @@ __device__ __forceinline__ void super_tile_cached(const TileArgs& a, int sr, int
     constexpr int NR = 2 * RW * NV;
     constexpr int NB = 2 * PF;           // register buffers (tiles in flight + 1)
     static_assert(SC % NB == 0, "buffer rotation");
-    const int sct = a.se;                // column tiles per super-tile: a multiple
-    const int SR = 64 * sct / TR;        // of NB (the launcher checks), TR <= edge
+    constexpr int sct = SC;              // largest super-tiles only (the launcher checks)
+    constexpr int SR = 64 * sct / TR;
     using Entry = typename std::conditional<GEN == 0, float2, float>::type;
 
     const int lane = threadIdx.x & 63;
@@ -396,7 +396,6 @@ __device__ __forceinline__ void super_tile_cached(const TileArgs& a, int sr, int
 
 #pragma unroll
         for (int cc = 0; cc < SC; ++cc) {
-            if (cc >= sct) break;
             // prefetch PF tiles ahead: (rr, cc + PF) or (rr + 1, cc + PF - sct)
             if (cc + PF < sct) issue(rr, cc + PF);
             else if (more) issue(rr + 1, cc + PF - sct);
@@ -456,7 +455,6 @@ __device__ __forceinline__ void super_tile_cached(const TileArgs& a, int sr, int
     const int slot_t = diag_st ? a.n_super : sr;
 #pragma unroll
     for (int cc = 0; cc < SC; ++cc) {
-        if (cc >= sct) break;
 #pragma unroll
         for (int v = 0; v < NV; ++v) red[w][lane][v] = tr[cc][v];
         __syncthreads();
@@ -486,8 +484,8 @@ __global__ __launch_bounds__(256) void tile_apply_kernel(TileArgs a)
     super_tile<NV, RW, GEN, SRC>(a, st.x, st.y, red, xs);
 }
 
-// Single-vector products of a fully cached operator (tile shape 0), one tile
-// of prefetch.
+// Single-vector products of a fully cached operator (tile shape 0, 256-wide
+// super-tiles), one tile of prefetch.
 template <int RW, int GEN, int PF>
 __global__ __launch_bounds__(256, 3) void tile_apply_cached_kernel(TileArgs a)
 {
@@ -606,8 +604,9 @@ hipError_t launch_nv(const TileArgs& a, int n_st, hipStream_t s)
     const bool cached = a.src.pair_slot != nullptr;
     const dim3 g(n_st), b(256);
     if constexpr (NV == 1 && RW == 8) {
-        // single vector, fully cached, tile shape 0, even edge: pipelined reads
-        if (cached && a.src.all_cached && a.se % 2 == 0) {
+        // single vector, fully cached, tile shape 0, 256-wide super-tiles:
+        // pipelined reads
+        if (cached && a.src.all_cached && a.se == kSuper / 64) {
             if (a.src.gen == 0)
                 hipLaunchKernelGGL((tile_apply_cached_kernel<RW, 0, 1>), g, b, 0, s, a);
             else

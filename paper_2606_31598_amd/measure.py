@@ -1,6 +1,6 @@
 """Timings of the product on the paper's configurations (one MI355X).
 
-    python -m paper_2606_31598_amd.measure c0|c2|c3 [--reps N]
+    python -m paper_2606_31598_amd.measure c0|c2|c3|modes [--reps N]
 
 Each sub-command prints JSON lines with the measured quantities of one
 configuration; accuracy against the binary64 reference lives in the tests.
@@ -14,6 +14,9 @@ configuration; accuracy against the binary64 reference lives in the tests.
 * c3 -- Philox-GUE D = 262144, 16 vectors, b = 512: procedural and 25%
   canonical cache, binary32 and split-bfloat16 matrix-core products; cache
   fill time and the bandwidth of the cached part.
+* modes -- single-vector products of one operator (Philox-GUE or sinc-DVR,
+  D = 32768 by default, b = 256) in each storage mode: procedural, 50%
+  canonical cache, full cache; cache bytes and the rate they are read at.
 """
 import argparse
 import json
@@ -146,12 +149,36 @@ def c3(reps):
             torch.cuda.synchronize()
 
 
+def modes(reps, family="gue", D=32768):
+    torch = _cuda()
+    from . import procmv as pm, workloads
+    X = torch.from_numpy(workloads.gaussian_vectors(D, 1, seed=2).astype(np.complex64)).cuda()
+    Y = torch.empty_like(X)
+    for name, strat, f in (("procedural", pm.PROCEDURAL, 0.0), ("partial 0.5", pm.PARTIAL, 0.5),
+                           ("full", pm.FULL, 1.0)):
+        op = pm.Operator.gue(D, seed=1) if family == "gue" else pm.Operator.dvr(D)
+        op.plan(256, strat, f)
+        info = op.plan_info()
+        t = _time(lambda: op.apply(X, Y), reps, torch)
+        _emit({"config": "modes", "workload": f"{family} D={D} b=256, 1 vector", "strategy": name,
+               "us_per_product": t * 1e6, "gelem_s": D * D / t / 1e9,
+               "cache_gb": info["cache_bytes"] / 1e9,
+               "cache_read_gb_s": info["cache_bytes"] / t / 1e9})
+        op.close()
+        torch.cuda.synchronize()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["c0", "c2", "c3"])
+    ap.add_argument("cmd", choices=["c0", "c2", "c3", "modes"])
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--family", choices=["gue", "dvr"], default="gue")
+    ap.add_argument("--D", type=int, default=32768)
     args = ap.parse_args(argv)
-    {"c0": c0, "c2": c2, "c3": c3}[args.cmd](args.reps)
+    if args.cmd == "modes":
+        modes(args.reps, args.family, args.D)
+    else:
+        {"c0": c0, "c2": c2, "c3": c3}[args.cmd](args.reps)
 
 
 if __name__ == "__main__":

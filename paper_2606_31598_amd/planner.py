@@ -123,7 +123,7 @@ def t_total(tf, ta, reuse):
     return tf + reuse * ta
 
 
-def training_set(table, draws=2, seed=1234):
+def training_set(table, draws=4, seed=1234):
     """One record per (measured trial, draw of budget and reuse): features of
     the pair and the measured total time t_fill + reuse t_apply (ms)."""
     rng = np.random.default_rng(seed)
@@ -142,8 +142,8 @@ def training_set(table, draws=2, seed=1234):
     return np.array(X, np.float32), np.array(y, np.float32)
 
 
-def train(table, epochs=4000, lr=3e-3, seed=0):
-    X, y = training_set(table)
+def train(table, epochs=4000, lr=3e-3, seed=0, draws=4):
+    X, y = training_set(table, draws=draws)
     mu = X.mean(0)
     sd = X.std(0)
     sd[sd == 0] = 1.0
@@ -158,7 +158,7 @@ def train(table, epochs=4000, lr=3e-3, seed=0):
     params, hist = pm.mlp_train(Z, y, p, epochs, lr)
     pred = pm.mlp_predict(params, Z)
     return {"params": params.tolist(), "norm": np.concatenate([mu, sd]).tolist(),
-            "n_train": int(y.size), "epochs": epochs, "lr": lr,
+            "n_train": int(y.size), "draws": draws, "epochs": epochs, "lr": lr,
             "train_log_mse": float(np.mean((pred - y) ** 2)),
             "loss_first": float(hist[0]), "loss_last": float(hist[-1])}
 
@@ -214,12 +214,13 @@ def main(argv=None):
     ap.add_argument("--families", default="0,1")
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--max-log2d", type=int, default=18)
+    ap.add_argument("--nvecs", default=",".join(str(v) for v in NVECS))
     args = ap.parse_args(argv)
     if args.cmd in ("collect", "all"):
         out = args.out or args.trials
         fams = tuple(int(f) for f in args.families.split(","))
         n = collect(out, log2_d=range(args.min_log2d, args.max_log2d + 1), families=fams,
-                    reps=args.reps)
+                    nvecs=tuple(int(v) for v in args.nvecs.split(",")), reps=args.reps)
         log(f"{n} trials written to {out}")
         args.trials = out
     if args.cmd in ("train", "all"):

@@ -62,7 +62,7 @@ def test_trained_network_matches_oracle_forward():
     norm = np.asarray(model["norm"], np.float64)
     mu, sd = norm[:8], norm[8:]
     _, table = planner.load_trials(TRIALS)
-    X, y = planner.training_set(table)
+    X, y = planner.training_set(table, draws=model.get("draws", 2))
     assert X.shape[0] == model["n_train"]
     pred = opl.mlp_forward(p, (X.astype(np.float64) - mu) / sd)[0]
     mse = float(np.mean((pred - y) ** 2))
