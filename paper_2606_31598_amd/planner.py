@@ -69,6 +69,14 @@ def model_from(d):
     return mm
 
 
+def load_planners(trials=DEFAULT_TRIALS, model=DEFAULT_MODEL):
+    """The calibrated analytic model and the trained network (parameters and
+    feature normalisation) for procmv_plan_choose / procmv_plan_auto."""
+    m = json.load(open(model))
+    mm = model_from(m["machine_model"]) if "machine_model" in m else load_trials(trials)[0]
+    return mm, np.array(m["params"], np.float32), np.array(m["norm"], np.float32)
+
+
 def collect(out_path, log2_d=LOG2_D, nvecs=NVECS, families=(0, 1), reps=2):
     """Measure fill and product time of every memory-feasible candidate on the
     (D, nvec, family) grid; one JSON line per trial."""

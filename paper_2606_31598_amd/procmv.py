@@ -320,6 +320,19 @@ class Operator:
                                   _stream(stream)))
         return self
 
+    def plan_auto(self, nvec, budget_bytes, reuse, planner=1, mm=None, params=None,
+                  norm=None, stream=None):
+        """Choose the plan with the analytic (0) or learned (1) planner and
+        apply it (binary32); returns the chosen candidate index."""
+        idx = ctypes.c_int32()
+        pa = _f32(params) if params is not None else (None, None)   # keep the arrays alive
+        na = _f32(norm) if norm is not None else (None, None)
+        _check(load().procmv_plan_auto(self._h, int(nvec), float(budget_bytes), int(reuse),
+                                       int(planner),
+                                       ctypes.byref(mm) if mm is not None else None,
+                                       pa[1], na[1], _stream(stream), ctypes.byref(idx)))
+        return idx.value
+
     def plan_info(self) -> dict:
         info = PlanInfo()
         _check(load().procmv_plan_info(self._h, ctypes.byref(info)))

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import planner as opl
+from tests.gpu_util import rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -83,3 +84,29 @@ def test_trained_planner_beats_fixed_plan(pm):
     assert res["n_workloads"] >= 150
     assert res["learned"]["mean_regret"] < res["procedural"]["mean_regret"]
     assert res["learned"]["within_10pct"] >= res["procedural"]["within_10pct"]
+
+
+def test_plan_auto_learned_and_analytic(pm, orc):
+    """procmv_plan_auto plans the candidate procmv_plan_choose ranks first,
+    and the planned operator's product matches the binary64 oracle."""
+    import torch
+    trials = os.path.join(DATA, "mi355x_plan_trials.jsonl")
+    model_path = os.path.join(DATA, "mi355x_planner_mlp.json")
+    if not (os.path.exists(trials) and os.path.exists(model_path)):
+        pytest.skip("no measured plan trials / trained model committed")
+    from paper_2606_31598_amd import planner, workloads
+    mm, params, norm = planner.load_planners(trials, model_path)
+    D = 3000
+    X = workloads.gaussian_vectors(D, 2, seed=11)
+    ref = orc.gue_apply_rows(5, D, X)
+    for which, budget, reuse in ((1, 64e9, 300), (1, 16e9, 1), (0, 64e9, 300)):
+        op = pm.Operator.gue(D, seed=5)
+        idx = op.plan_auto(2, budget, reuse, planner=which, mm=mm, params=params, norm=norm)
+        want, _ = pm.plan_choose(which, D, 2, budget, reuse, 0, mm=mm, params=params, norm=norm)
+        assert idx == want
+        b, st, f = pm.plan_candidates()[idx]
+        info = op.plan_info()
+        assert info["block_size"] == b
+        got = op.apply(torch.from_numpy(X.astype(np.complex64)).cuda()).cpu().numpy()
+        assert rel_l2(got, ref) <= 1e-5
+        op.close()
