@@ -745,6 +745,25 @@ procmv_status procmv_get_entries(procmv_op_t H, int64_t r0, int64_t c0,
     return PROCMV_OK;
 }
 
+procmv_status procmv_selftest_generator(int32_t* ln_mismatches, int32_t* sqrt_mismatches,
+                                        void* stream)
+{
+    if (!ln_mismatches || !sqrt_mismatches) return fail(PROCMV_ERR_INVALID_ARG, "null output");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned* d = nullptr;
+    if (hipMalloc((void**)&d, 2 * sizeof(unsigned)) != hipSuccess)
+        return fail(PROCMV_ERR_OOM, "self-test counters");
+    unsigned h[2] = {0u, 0u};
+    hipError_t e = launch_selftest_generator(d, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(PROCMV_ERR_HIP, "self-test: %s", hipGetErrorString(e));
+    *ln_mismatches = (int32_t)h[0];
+    *sqrt_mismatches = (int32_t)h[1];
+    return PROCMV_OK;
+}
+
 procmv_status procmv_profile_enable(procmv_op_t H, int32_t every)
 {
     procmv_status st = check_op(H);

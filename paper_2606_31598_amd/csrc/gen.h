@@ -56,8 +56,38 @@ __device__ __forceinline__ float u01(uint32_t x)
     return (float)((x >> 9) * 2u + 1u) * 5.9604644775390625e-8f;
 }
 
+// Correctly rounded binary32 a / b and sqrt(a) on the generator's domain.
+// The quotient is a reciprocal estimate refined by one residual correction
+// (q0 = a y, r = a - q0 b exactly by FMA, q = q0 + r y); the root is the
+// hardware estimate moved by at most one ulp to the side that leaves the
+// smaller residual.  Neither handles denormal, infinite or NaN operands,
+// which the generator never produces (b in [1.7, 2.5], a in [1.2e-7, 33.3]);
+// procmv_selftest_generator checks both against IEEE division and square
+// root for every one of the 2^23 uniforms the generator can draw.
+__device__ __forceinline__ float div_gen(float a, float b)
+{
+    const float y = __builtin_amdgcn_rcpf(b);
+    const float q0 = a * y;
+    const float r = __builtin_fmaf(-q0, b, a);
+    return __builtin_fmaf(r, y, q0);
+}
+
+__device__ __forceinline__ float sqrt_gen(float a)
+{
+    float s = __builtin_amdgcn_sqrtf(a);
+    const float sm = __uint_as_float(__float_as_uint(s) - 1u);
+    const float sp = __uint_as_float(__float_as_uint(s) + 1u);
+    const float rm = __builtin_fmaf(-sm, s, a);
+    const float rp = __builtin_fmaf(-sp, s, a);
+    s = (rm <= 0.f) ? sm : s;
+    s = (rp > 0.f) ? sp : s;
+    return s;
+}
+
 // ln u for u in (0, 1): u = 2^e m with m in [sqrt(1/2), sqrt(2)];
-// ln m = 2 atanh(s), s = (m - 1)/(m + 1), odd series through s^9.
+// ln m = 2 atanh(s), s = (m - 1)/(m + 1), odd series through s^9.  IEEE
+// selects the compiler's general division (the self-test's reference).
+template <bool IEEE = false>
 __device__ __forceinline__ float ln_unit(float u)
 {
     uint32_t b = __float_as_uint(u);
@@ -68,7 +98,7 @@ __device__ __forceinline__ float ln_unit(float u)
         e = e + 1;
     }
     float f = m - 1.0f;
-    float s = f / (2.0f + f);
+    float s = IEEE ? f / (2.0f + f) : div_gen(f, 2.0f + f);
     float s2 = s * s;
     float p = __builtin_fmaf(s2, (float)(2.0 / 9.0), (float)(2.0 / 7.0));
     p = __builtin_fmaf(s2, p, (float)(2.0 / 5.0));
@@ -111,7 +141,7 @@ __device__ __forceinline__ void box_muller(uint32_t x0, uint32_t x1, float& z0,
                                            float& z1)
 {
     float l = ln_unit(u01(x0));
-    float r = __builtin_sqrtf(-2.0f * l);
+    float r = sqrt_gen(-2.0f * l);
     float sv, cv;
     sincos_turn(u01(x1), sv, cv);
     z0 = r * cv;

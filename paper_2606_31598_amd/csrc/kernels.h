@@ -188,6 +188,10 @@ hipError_t launch_cache_fill(const SourceArgs& src, int32_t D,
 hipError_t launch_get_entries(const SourceArgs& src, int64_t r0, int64_t c0,
                               int32_t nr, int32_t nc, float2* out,
                               hipStream_t s);
+// Generator arithmetic self-test (defined in selftest.hip): count[0] = uniforms
+// whose logarithm differs from the IEEE-division one, count[1] = square roots
+// that differ from IEEE sqrt.
+hipError_t launch_selftest_generator(unsigned* count, hipStream_t s);
 // Sinc-DVR Toeplitz product (defined in dvr.hip).
 int dvr_toeplitz_variant(int32_t D, int nv);
 int dvr_toeplitz_chunk_of(int variant);

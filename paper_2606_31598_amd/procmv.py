@@ -23,7 +23,8 @@ _STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "INFEASIBLE_PLAN",
 EXPORTS = [
     "procmv_create_operator", "procmv_plan", "procmv_apply",
     "procmv_spectral_bounds", "procmv_cheb_order",
-    "procmv_chebyshev_propagate", "procmv_get_entries", "procmv_plan_info",
+    "procmv_chebyshev_propagate", "procmv_get_entries", "procmv_selftest_generator",
+    "procmv_plan_info",
     "procmv_destroy", "procmv_last_error", "procmv_profile_enable",
     "procmv_profile_read", "procmv_autotune", "procmv_batch_create",
     "procmv_batch_info", "procmv_batch_configure", "procmv_batch_apply",
@@ -87,6 +88,7 @@ def load():
                                              c.c_double, c.c_int32, c.c_int32,
                                              c.c_double, c.c_double,
                                              c.POINTER(c.c_double), vp]
+    L.procmv_selftest_generator.argtypes = [c.POINTER(c.c_int32), c.POINTER(c.c_int32), vp]
     L.procmv_get_entries.argtypes = [vp, c.c_int64, c.c_int64, c.c_int32,
                                      c.c_int32, vp, vp]
     L.procmv_plan_info.argtypes = [vp, c.POINTER(PlanInfo)]
@@ -179,6 +181,14 @@ def cheb_order(x: float, tol: float = 1e-10) -> int:
 def _f32(a):
     a = np.ascontiguousarray(a, dtype=np.float32)
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def selftest_generator(stream=None):
+    """(logarithm, square-root) bitwise mismatches of the generator's short
+    division and square root against IEEE, over all 2^23 uniforms."""
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().procmv_selftest_generator(ctypes.byref(a), ctypes.byref(b), _stream(stream)))
+    return a.value, b.value
 
 
 def plan_candidates():

@@ -38,6 +38,12 @@ def test_gue_entries_bit_exact(pm, orc, D, win):
     assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
 
 
+def test_generator_short_arithmetic_matches_ieee(pm):
+    """The kernels' short division and square root give the IEEE results on
+    every one of the 2^23 uniforms the generator can draw (exhaustive)."""
+    assert pm.selftest_generator() == (0, 0)
+
+
 def test_dvr_entries_bit_exact(pm, orc):
     D = 4096
     op = pm.Operator.dvr(D)
