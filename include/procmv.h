@@ -192,19 +192,22 @@ procmv_status procmv_autotune(procmv_op_t H, int32_t nvec, int32_t reps,
  * vector block) explicitly, or -1 for the default that procmv_plan sets: the
  * super-tiles whose canonical pairs are all cached use shape 0 (narrow tiles
  * streaming the cache), those with none cached shape 2 for the Philox-GUE
- * generator on 256-wide super-tiles (wide tiles) and 0 otherwise, mixed ones (block size
- * below the super-tile edge) shape 0, one launch per class.  Shapes whose
- * tile rows exceed the super-tile edge (64 entries for D <= 5632, 128 for
- * D <= 11264, else 256) are reduced to the largest that fits.  With one explicit shape, products are bit-identical across storage
+ * generator on 256-wide super-tiles (wide tiles) and 0 otherwise, mixed ones
+ * (block size below the super-tile edge) shape 0, one launch per class.
+ * Shapes whose tile rows exceed the super-tile edge (64 entries for
+ * D <= 5632, 128 for D <= 11264, else 256) are reduced to the largest that
+ * fits.  With one explicit shape, products are bit-identical across storage
  * modes and block sizes. */
 procmv_status procmv_set_tile_shape(procmv_op_t H, int32_t shape);
 
 /* Measured microbenchmark of one (operator, plan) pair (paper Sec. IV-C,
- * Eq. measured_matvec_time): creates the operator, times procmv_plan
- * (allocation and cache fill) and the mean of `reps` products of nvec
- * vectors after `warmup` untimed ones, then releases everything.  Times in
- * ms (host outputs).  Returns PROCMV_ERR_OOM when the plan or the vectors do
- * not fit.  SYNCHRONISES the stream. */
+ * Eq. measured_matvec_time): creates the operator, plans it, times the cache
+ * fill (the fill kernels re-run on the allocated slots: allocation is left
+ * out, its time depends on the allocator's history) and the mean of `reps`
+ * products of nvec vectors after `warmup` untimed ones, then releases
+ * everything.  Times in ms (host outputs; fill 0 without a cache).  Returns
+ * PROCMV_ERR_OOM when the plan or the vectors do not fit.  SYNCHRONISES the
+ * stream. */
 procmv_status procmv_measure(procmv_generator gen, uint64_t seed, int64_t D,
                              const void* gen_params, int32_t nvec,
                              int32_t block_size, procmv_strategy strategy,

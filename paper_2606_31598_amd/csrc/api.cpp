@@ -264,9 +264,21 @@ struct TileOut {
 // Whether a block of `remaining` vectors goes to the matrix cores: always in
 // split-bf16 precision, and in binary32 once there are enough vectors for the
 // per-tile product to be a contraction worth a GEMM.
+// Matrix-core path for vector blocks: always in split-bf16 precision; in
+// binary32 from 4 vectors on (measured on MI355X: from 4 vectors the MFMA
+// kernel beats the VALU tile kernel in every storage mode), except for the
+// procedural sinc-DVR operator, whose Toeplitz kernel (up to 8 vectors per
+// launch) is 5-10 times faster than either.
+bool mfma_path(int gen, bool procedural, int precision, int nv)
+{
+    if (precision == PROCMV_SPLIT_BF16) return true;
+    if (gen == 1 && procedural) return false;
+    return nv >= 4;
+}
+
 bool use_mfma(const procmv_op* op, int remaining)
 {
-    return op->precision == PROCMV_SPLIT_BF16 || remaining >= 8;
+    return mfma_path(op->gen, op->p_cache == 0, op->precision, remaining);
 }
 
 // Vectors handled by one tile launch.
@@ -1329,14 +1341,20 @@ procmv_status procmv_measure(procmv_generator gen, uint64_t seed, int64_t D,
             return fail(PROCMV_ERR_HIP, "event creation failed: %s", hipGetErrorString(ee));
         }
     }
-    // fill time: the plan call (allocation + cache fill, synchronised)
-    if (hipEventRecord(e0, s) != hipSuccess) { cleanup(); return fail(PROCMV_ERR_HIP, "event"); }
     st = procmv_plan(H, block_size, strategy, cache_fraction, precision, stream);
     if (st != PROCMV_OK) { cleanup(); return st; }
-    (void)hipEventRecord(e1, s);
-    (void)hipEventSynchronize(e1);
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (t_fill_ms) *t_fill_ms = ms;
+    // fill time: the fill kernels once more on the allocated slots
+    if (t_fill_ms) *t_fill_ms = 0.0;
+    if (H->p_cache > 0) {
+        if (hipEventRecord(e0, s) != hipSuccess) { cleanup(); return fail(PROCMV_ERR_HIP, "event"); }
+        const hipError_t fe = launch_cache_fill(H->source(), (int32_t)D, H->d_pairs, H->p_cache,
+                                                H->d_slots, s);
+        if (fe != hipSuccess) { cleanup(); return fail(PROCMV_ERR_HIP, "fill: %s", hipGetErrorString(fe)); }
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (t_fill_ms) *t_fill_ms = ms;
+    }
     if (hipMalloc(&X, bytes) != hipSuccess || hipMalloc(&Y, bytes) != hipSuccess) {
         (void)hipGetLastError();
         cleanup();
@@ -1494,8 +1512,9 @@ void plan_memory(int64_t D, int32_t nvec, int family, int32_t b, int32_t strateg
     const double be = family == 0 ? 8.0 : 4.0;
     m_op = (double)p * b * b * be;
     const int64_t ns = (D + 64 * super_edge_tiles(D) - 1) / (64 * super_edge_tiles(D));
-    const int chunk = nvec >= 8 ? 16 : nvec >= 4 ? 4 : nvec >= 2 ? 2 : 1;
-    const double slots = (family == 1 && strategy == PROCMV_PROCEDURAL && nvec < 8)
+    const bool mfma = mfma_path(family, strategy == PROCMV_PROCEDURAL, PROCMV_FP32, nvec);
+    const int chunk = mfma ? 16 : nvec >= 8 ? 8 : nvec >= 4 ? 4 : nvec >= 2 ? 2 : 1;
+    const double slots = (family == 1 && strategy == PROCMV_PROCEDURAL && !mfma)
                              ? (double)((D + 511) / 512) : (double)(ns + 1);
     m_work = slots * chunk * D * 8.0 + 2.0 * nvec * D * 8.0;
     if (reuse > 1) m_work += (double)nvec * D * (8.0 + 16.0);
@@ -1564,8 +1583,10 @@ procmv_status procmv_plan_model_time(const procmv_machine_model* mm, int64_t D, 
     const double cached_entries = mo / be;
     const double canon = 0.5 * (double)D * (double)(D + 1);
     const double gen_entries = std::max(0.0, canon - cached_entries);
-    const bool mfma = nvec >= 8;
-    const int chunks = mfma ? (nvec + 15) / 16 : (nvec + 7) / 8;
+    const bool mfma = mfma_path(family, strategy == PROCMV_PROCEDURAL, PROCMV_FP32, nvec);
+    int chunks = 0;                 // launches: blocks of 16 (MFMA) or 8/4/2/1 (VALU)
+    for (int r = nvec; r > 0; ++chunks)
+        r -= mfma ? std::min(r, 16) : r >= 8 ? 8 : r >= 4 ? 4 : r >= 2 ? 2 : 1;
     double t_src;
     if (family == 1 && strategy == PROCMV_PROCEDURAL && !mfma)
         t_src = (double)D * D * nvec / mm->dvr_rate;   // Toeplitz kernel, per vector

@@ -110,3 +110,14 @@ def test_plan_auto_learned_and_analytic(pm, orc):
         got = op.apply(torch.from_numpy(X.astype(np.complex64)).cuda()).cpu().numpy()
         assert rel_l2(got, ref) <= 1e-5
         op.close()
+
+
+def test_measure_reports_fill_and_product_times(pm):
+    """procmv_measure: the fill time is that of the cache fill (zero without a
+    cache, growing with the cached pairs) and the product time is positive."""
+    D = 8192
+    tf0, ta0 = pm.measure(pm.GEN_PHILOX_GUE, D, 1, 256, pm.PROCEDURAL, reps=2)
+    tf5, ta5 = pm.measure(pm.GEN_PHILOX_GUE, D, 1, 256, pm.PARTIAL, 0.5, reps=2)
+    tf1, ta1 = pm.measure(pm.GEN_PHILOX_GUE, D, 1, 256, pm.FULL, 1.0, reps=2)
+    assert tf0 == 0.0 and ta0 > 0 and ta5 > 0 and ta1 > 0
+    assert 0 < tf5 < tf1
