@@ -302,7 +302,7 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
     const int chunk = toeplitz ? dvr_toeplitz_chunk_of(variant) : 1;
     out.n_slots = toeplitz ? (int32_t)((op->D + chunk - 1) / chunk) : op->n_super + 1;
     out.vdiag = toeplitz ? op->d_v : nullptr;
-    out.nv_stride = mfma ? 16 : nv;
+    out.nv_stride = nv;
     const size_t need = (size_t)out.n_slots * out.nv_stride * ldp * sizeof(float2);
     procmv_status st = ensure(op->d_P, op->P_bytes, need);
     if (st != PROCMV_OK) return st;
@@ -915,8 +915,15 @@ procmv_status batch_tiles(procmv_batch* B, const float2* xbase, hipStream_t s)
     L.grid = (int)std::min<int64_t>(B->grid, B->n_items);
     L.cached = 0;
     L.min_se = kSuper / 64;
-    for (procmv_op* op : B->ops) L.cached |= (op->p_cache > 0) ? 1 : 0;
-    HIP_TRY(launch_tile_apply_batched(L, s));
+    bool all_cached = true;
+    for (procmv_op* op : B->ops) {
+        L.cached |= (op->p_cache > 0) ? 1 : 0;
+        all_cached = all_cached && op->p_cache > 0;
+    }
+    // the single-operator routing rule, for the batch as a whole
+    L.mfma = mfma_path(B->gen, !all_cached, PROCMV_FP32, B->nv) ? 1 : 0;
+    if (L.mfma) HIP_TRY(launch_tile_mfma_batched(L, s));
+    else HIP_TRY(launch_tile_apply_batched(L, s));
     return PROCMV_OK;
 }
 
@@ -1513,6 +1520,8 @@ void plan_memory(int64_t D, int32_t nvec, int family, int32_t b, int32_t strateg
     m_op = (double)p * b * b * be;
     const int64_t ns = (D + 64 * super_edge_tiles(D) - 1) / (64 * super_edge_tiles(D));
     const bool mfma = mfma_path(family, strategy == PROCMV_PROCEDURAL, PROCMV_FP32, nvec);
+    // vector block of one launch (the matrix-core block is counted at its
+    // largest, 16: a bound on the partial buffer for every nvec)
     const int chunk = mfma ? 16 : nvec >= 8 ? 8 : nvec >= 4 ? 4 : nvec >= 2 ? 2 : 1;
     const double slots = (family == 1 && strategy == PROCMV_PROCEDURAL && !mfma)
                              ? (double)((D + 511) / 512) : (double)(ns + 1);

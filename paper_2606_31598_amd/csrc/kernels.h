@@ -60,6 +60,7 @@ struct BatchTileLaunch {
     int gen, nv, shape, grid;
     int cached;               // some instance has cached block pairs
     int min_se;               // smallest super-tile edge (64-column tiles) of the instances
+    int mfma;                 // matrix-core kernel (binary32) instead of the VALU one
 };
 
 // Sinc-DVR Toeplitz product: row bands x column chunks, one partial slot per
@@ -182,6 +183,8 @@ hipError_t launch_reduce(const ReduceArgs& a, Epi mode, hipStream_t s,
 // precision 0 = binary32 MFMA, 1 = split bfloat16.
 hipError_t launch_tile_mfma(const TileArgs& a, int precision, int n_st,
                             hipStream_t s);
+// Batched persistent matrix-core product (binary32) of the items of a batch.
+hipError_t launch_tile_mfma_batched(const BatchTileLaunch& b, hipStream_t s);
 hipError_t launch_cache_fill(const SourceArgs& src, int32_t D,
                              const int2* pairs, int64_t n_pairs, void* slots,
                              hipStream_t s);
