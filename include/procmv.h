@@ -302,9 +302,12 @@ procmv_status procmv_mlp_predict(const float* params, const float* z,
  * and must outlive the batch.  Vectors are PACKED in one device complex64
  * buffer: instance k holds nvec vectors of length D_k, each contiguous,
  * starting at element off_k = sum_{l<k} nvec * D_l.  One persistent launch
- * walks every (instance, super-tile) item; a second launch reduces all
- * partials in a fixed order, so a batched product is bit-identical to the
- * per-instance products with the same tile shape. */
+ * walks every (instance, super-tile) item (super-tiles of edge 256; on the
+ * matrix cores for 4 and 8 vectors, by the routing rule of procmv_apply);
+ * a second launch reduces all partials in a fixed order.  A batched product
+ * does not depend on the grid or the item order, and is bit-identical to an
+ * instance's own product when that runs the same kernel on the same
+ * super-tiles (same tile shape; D > 11264). */
 typedef struct procmv_batch* procmv_batch_t;
 
 /* nvec in {1, 2, 4, 8}.  Allocates the packed partial buffers. */
