@@ -128,3 +128,24 @@ def test_c2_batch_shape_autotuned(pm, orc):
     for k in np.argsort(sizes)[:3]:
         ref = orc.gue_apply_rows(int(k) + 1, int(sizes[k]), Xs[k])
         assert rel_l2(got[k], ref) <= 1e-5
+
+
+@pytest.mark.parametrize("strat,f", [(0, 0.0), (1, 0.5), (2, 1.0)])
+def test_batched_dvr_instances(pm, orc, strat, f):
+    """Sinc-DVR batches: procedural (VALU batched kernel with the closed-form
+    entries) and cached (matrix-core batched kernel, 4 vectors) against the
+    binary64 oracle, instance by instance."""
+    import torch
+    sizes = [300, 1000, 777, 2048]
+    nvec = 4
+    ops = [pm.Operator.dvr(D).plan(256, strat, f) for D in sizes]
+    B = pm.Batch(ops, nvec)
+    Xh = _packed(sizes, nvec, seed=9)
+    X = torch.from_numpy(Xh.astype(np.complex64)).cuda()
+    Y = torch.empty_like(X)
+    B.apply(X, Y)
+    got = _unpack(Y.cpu().numpy(), sizes, nvec)
+    Xs = _unpack(Xh, sizes, nvec)
+    for k, D in enumerate(sizes):
+        ref = orc.DVR(D).apply_rows(Xs[k])
+        assert rel_l2(got[k], ref) <= 1e-5, (D, strat)
