@@ -1489,7 +1489,7 @@ procmv_status procmv_mlp_predict(const float* params, const float* z, int32_t n,
 
 // ------------------------------------------------------------------------
 // Execution planner (paper Sec. IV: Algorithm 1 analytic, Algorithm 3
-// learned, and the measured exhaustive search that judges both).
+// learned, and the measured exhaustive search that scores both).
 // ------------------------------------------------------------------------
 namespace {
 

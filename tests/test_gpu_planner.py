@@ -3,7 +3,7 @@
 The hand-written MLP kernels must reproduce the binary64 oracle's gradients;
 training on the GPU must fit; and on held-out workloads the trained network
 must choose better plans than the fixed procedural plan (exhaustive measured
-search is the judge).
+search is the reference).
 """
 import json
 import os
