@@ -28,10 +28,11 @@ def pm():
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("D,nvec,strat,f,b", [
     (1000, 16, 0, 0.0, 256), (2048, 9, 1, 0.5, 256), (777, 20, 2, 1.0, 128),
-    (3001, 1, 0, 0.0, 512), (513, 4, 1, 0.25, 64)])
+    (3001, 1, 0, 0.0, 512), (513, 4, 1, 0.25, 64), (4500, 5, 2, 1.0, 256),
+    (6000, 8, 0, 0.0, 1024)])
 def test_gue_mfma_parity(pm, orc, prec, D, nvec, strat, f, b):
-    if prec == 0 and nvec < 8:
-        pytest.skip("binary32 with few vectors runs on the VALU kernel")
+    if prec == 0 and nvec < 4:
+        pytest.skip("binary32 with fewer than 4 vectors runs on the VALU kernel")
     op = pm.Operator.gue(D, seed=3).plan(b, strat, f, precision=prec)
     X = workloads.gaussian_vectors(D, nvec, seed=nvec + 1)
     got = to_host(op.apply(to_dev(X)))
