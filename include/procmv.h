@@ -189,11 +189,10 @@ procmv_status procmv_autotune(procmv_op_t H, int32_t nvec, int32_t reps,
                               void* stream, int32_t* shape_out, double* best_ms);
 
 /* Set the VALU tile shape (0, 1, 2: 8, 16, 32 direct values per lane and
- * vector block) explicitly, or -1 for the default that procmv_plan sets: the
- * super-tiles whose canonical pairs are all cached use shape 0 (narrow tiles
- * streaming the cache), those with none cached shape 2 for the Philox-GUE
- * generator on 256-wide super-tiles (wide tiles) and 0 otherwise, mixed ones
- * (block size below the super-tile edge) shape 0, one launch per class.
+ * vector block) explicitly, or -1 for the default that procmv_plan sets:
+ * shape 0 for every class of super-tiles (all canonical pairs cached, none
+ * cached, mixed when the block size is below the super-tile edge), one
+ * launch per class.
  * Shapes whose tile rows exceed the super-tile edge (64 entries for
  * D <= 5632, 128 for D <= 11264, else 256) are reduced to the largest that
  * fits.  With one explicit shape, products are bit-identical across storage
@@ -302,8 +301,8 @@ procmv_status procmv_mlp_predict(const float* params, const float* z,
  * and must outlive the batch.  Vectors are PACKED in one device complex64
  * buffer: instance k holds nvec vectors of length D_k, each contiguous,
  * starting at element off_k = sum_{l<k} nvec * D_l.  One persistent launch
- * walks every (instance, super-tile) item (super-tiles of edge 256; on the
- * matrix cores for 4 and 8 vectors, by the routing rule of procmv_apply);
+ * walks every (instance, super-tile) item (super-tiles of edge 256; VALU or
+ * matrix cores by the routing rule of procmv_apply);
  * a second launch reduces all partials in a fixed order.  A batched product
  * does not depend on the grid or the item order, and is bit-identical to an
  * instance's own product when that runs the same kernel on the same

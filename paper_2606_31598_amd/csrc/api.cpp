@@ -264,21 +264,24 @@ struct TileOut {
 // Whether a block of `remaining` vectors goes to the matrix cores: always in
 // split-bf16 precision, and in binary32 once there are enough vectors for the
 // per-tile product to be a contraction worth a GEMM.
-// Matrix-core path for vector blocks: always in split-bf16 precision; in
-// binary32 from 4 vectors on (measured on MI355X: from 4 vectors the MFMA
-// kernel beats the VALU tile kernel in every storage mode), except for the
-// procedural sinc-DVR operator, whose Toeplitz kernel (up to 8 vectors per
-// launch) is 5-10 times faster than either.
-bool mfma_path(int gen, bool procedural, int precision, int nv)
+// Matrix-core path for vector blocks (measured on MI355X, D = 32768): always
+// in split-bf16 precision; in binary32 for blocks of 8 or more vectors, and
+// for 4 to 7 vectors when every canonical pair is cached (the VALU tile
+// kernel generates faster up to 4 vectors: 2.0 against 3.1 ms for 4 GUE
+// vectors, but streams a full cache slower: 3.1 against 2.0 ms).  The
+// procedural sinc-DVR operator always takes the Toeplitz kernel (up to 8
+// vectors per launch), 5-10 times faster than either.
+bool mfma_path(int gen, bool procedural, bool all_cached, int precision, int nv)
 {
     if (precision == PROCMV_SPLIT_BF16) return true;
     if (gen == 1 && procedural) return false;
-    return nv >= 4;
+    return nv >= 8 || (nv >= 4 && all_cached);
 }
 
 bool use_mfma(const procmv_op* op, int remaining)
 {
-    return mfma_path(op->gen, op->p_cache == 0, op->precision, remaining);
+    return mfma_path(op->gen, op->p_cache == 0, op->p_cache == op->n_pair, op->precision,
+                     remaining);
 }
 
 // Vectors handled by one tile launch.
@@ -334,10 +337,8 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
             HIP_TRY(launch_tile_mfma(a, op->precision == PROCMV_SPLIT_BF16 ? 1 : 0,
                                      (int)op->n_st, s));
         } else {
-            // one launch per super-tile class; the default shape streams the
-            // cache with narrow tiles and generates Philox entries with wide
-            // ones on the largest super-tiles (sinc-DVR entries are table
-            // reads, and small super-tiles have few rows: narrow tiles)
+            // one launch per super-tile class (the cached class streams on
+            // the pipelined kernel); default tile shape 0 for every class
             const int64_t n_c = op->n_st_cached, n_g = op->n_st_gen;
             const int64_t n_m = op->n_st - n_c - n_g;
             const SourceArgs src = a.src;
@@ -351,8 +352,7 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
                 a.src.pair_slot = nullptr;
                 a.src.all_cached = 0;
                 a.st_list = op->d_st + n_c;
-                const int gshape = (op->gen == 0 && op->se == kSuper / 64) ? 2 : 0;
-                HIP_TRY(launch_tile_apply(a, nv, op->tile_shape >= 0 ? op->tile_shape : gshape,
+                HIP_TRY(launch_tile_apply(a, nv, op->tile_shape >= 0 ? op->tile_shape : 0,
                                           (int)n_g, s));
             }
             if (n_m > 0) {
@@ -915,13 +915,14 @@ procmv_status batch_tiles(procmv_batch* B, const float2* xbase, hipStream_t s)
     L.grid = (int)std::min<int64_t>(B->grid, B->n_items);
     L.cached = 0;
     L.min_se = kSuper / 64;
-    bool all_cached = true;
+    bool any_cached = false, all_full = true;
     for (procmv_op* op : B->ops) {
         L.cached |= (op->p_cache > 0) ? 1 : 0;
-        all_cached = all_cached && op->p_cache > 0;
+        any_cached = any_cached || op->p_cache > 0;
+        all_full = all_full && op->p_cache == op->n_pair;
     }
     // the single-operator routing rule, for the batch as a whole
-    L.mfma = mfma_path(B->gen, !all_cached, PROCMV_FP32, B->nv) ? 1 : 0;
+    L.mfma = mfma_path(B->gen, !any_cached, all_full, PROCMV_FP32, B->nv) ? 1 : 0;
     if (L.mfma) HIP_TRY(launch_tile_mfma_batched(L, s));
     else HIP_TRY(launch_tile_apply_batched(L, s));
     return PROCMV_OK;
@@ -1040,9 +1041,7 @@ procmv_status procmv_batch_create(const procmv_op_t* ops, int32_t n, int32_t nve
     BTRY(hipMalloc((void**)&B->d_off, n * sizeof(int64_t)));
     BTRY(hipMemcpy(B->d_off, B->off.data(), n * sizeof(int64_t), hipMemcpyHostToDevice));
 #undef BTRY
-    bool any_cache = false;
-    for (procmv_op* op : B->ops) any_cache |= op->p_cache > 0;
-    B->shape = any_cache ? 0 : 2;   // same default rule as single operators
+    B->shape = 0;                   // same default as single operators
     st = batch_upload_items(B);
     if (st != PROCMV_OK) {
         delete B;
@@ -1519,7 +1518,8 @@ void plan_memory(int64_t D, int32_t nvec, int family, int32_t b, int32_t strateg
     const double be = family == 0 ? 8.0 : 4.0;
     m_op = (double)p * b * b * be;
     const int64_t ns = (D + 64 * super_edge_tiles(D) - 1) / (64 * super_edge_tiles(D));
-    const bool mfma = mfma_path(family, strategy == PROCMV_PROCEDURAL, PROCMV_FP32, nvec);
+    const bool mfma = mfma_path(family, strategy == PROCMV_PROCEDURAL, strategy == PROCMV_FULL,
+                                PROCMV_FP32, nvec);
     // vector block of one launch (the matrix-core block is counted at its
     // largest, 16: a bound on the partial buffer for every nvec)
     const int chunk = mfma ? 16 : nvec >= 8 ? 8 : nvec >= 4 ? 4 : nvec >= 2 ? 2 : 1;
@@ -1592,7 +1592,8 @@ procmv_status procmv_plan_model_time(const procmv_machine_model* mm, int64_t D, 
     const double cached_entries = mo / be;
     const double canon = 0.5 * (double)D * (double)(D + 1);
     const double gen_entries = std::max(0.0, canon - cached_entries);
-    const bool mfma = mfma_path(family, strategy == PROCMV_PROCEDURAL, PROCMV_FP32, nvec);
+    const bool mfma = mfma_path(family, strategy == PROCMV_PROCEDURAL, strategy == PROCMV_FULL,
+                                PROCMV_FP32, nvec);
     int chunks = 0;                 // launches: blocks of 16 (MFMA) or 8/4/2/1 (VALU)
     for (int r = nvec; r > 0; ++chunks)
         r -= mfma ? std::min(r, 16) : r >= 8 ? 8 : r >= 4 ? 4 : r >= 2 ? 2 : 1;

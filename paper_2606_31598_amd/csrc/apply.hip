@@ -70,8 +70,16 @@ __device__ __forceinline__ float wave_reduce_scatter(float (&v)[N])
 #pragma unroll
         for (int k = 0; k < half; ++k) {
             const bool up = lane & mask;
-            const float keep = up ? v[half + k] : v[k];
-            const float give = up ? v[k] : v[half + k];
+            float keep, give;
+            if (N <= 32) {
+                // select values, not addresses: keeps the array in registers
+                const float lo = v[k], hi = v[half + k];
+                keep = up ? hi : lo;
+                give = up ? lo : hi;
+            } else {
+                keep = up ? v[half + k] : v[k];
+                give = up ? v[k] : v[half + k];
+            }
             v[k] = keep + __shfl_xor(give, mask);
         }
     }

@@ -58,7 +58,7 @@ def test_batched_apply_equals_per_instance(pm, orc, nvec):
         Xk = X[int(B.offsets[k]):int(B.offsets[k]) + nvec * D].view(nvec, D)
         singles.append(op.apply(Xk).cpu().numpy())
     outs = {}
-    for cfg in [(2, 1024, 0), (2, 256, 1), (0, 256, 1), (1, 2048, 0)]:
+    for cfg in [(2, 1024, 0), (2, 256, 1), (0, 256, 1), (0, 2048, 0), (1, 2048, 0)]:
         B.configure(*cfg)
         B.apply(X, Y)
         got = _unpack(Y.cpu().numpy(), sizes, nvec)
@@ -66,12 +66,13 @@ def test_batched_apply_equals_per_instance(pm, orc, nvec):
         for k, D in enumerate(sizes):
             assert rel_l2(got[k], refs[k]) <= 1e-5, (cfg, D)
             assert rel_l2(got[k], singles[k]) <= 1e-5, (cfg, D)
-        if cfg[0] == 2 or nvec == 4:
-            # one vector: procedural operators default to tile shape 2; four
-            # vectors: the matrix-core kernel in both (no tile shape); the
-            # D = 11520 operator plans the batch's super-tile edge too
+        if cfg[0] == 0:
+            # single products default to tile shape 0; the D = 11520 operator
+            # plans the batch's super-tile edge too
             assert np.array_equal(got[-1], singles[-1])
     for a, b in zip(outs[(2, 1024, 0)], outs[(2, 256, 1)]):
+        assert np.array_equal(a, b)
+    for a, b in zip(outs[(0, 256, 1)], outs[(0, 2048, 0)]):
         assert np.array_equal(a, b)
 
 
