@@ -116,6 +116,34 @@ procmv_status procmv_apply(procmv_op_t H, const void* X, int64_t ldx,
  * E_min = 0, E_max = pi^2/(2 mass dx^2) + max V. */
 procmv_status procmv_spectral_bounds(procmv_op_t H, double* c, double* R);
 
+/* Largest Lanczos step count accepted by procmv_lanczos_bounds. */
+#define PROCMV_LANCZOS_MAX_STEPS 256
+
+/* Matrix-free Lanczos estimate of the spectral bounds (paper Sec. VII: a short
+ * Lanczos run, m = 40 in the paper, gives E_min and E_max and hence the
+ * Chebyshev shift c = (E_max + E_min)/2 and half-width R = (E_max - E_min)/2).
+ * Plain three-term recurrence without reorthogonalisation from the start
+ * vector v0: v_1 = v0/||v0||, w = H v_j, alpha_j = Re <v_j, w>,
+ * w -= alpha_j v_j + beta_{j-1} v_{j-1}, beta_j = ||w||, v_{j+1} = w/beta_j.
+ * The products run in the tile kernels of the current plan (binary32 entries
+ * and vectors); inner products and norms are binary64; the m x m tridiagonal
+ * eigenproblem is solved on the host.  The extreme Ritz values are widened by
+ * their residual estimates |beta_m s_m| (s = unit eigenvector of T_m):
+ *   bounds_out (HOST, 6 doubles): E_min, E_max, theta_min, theta_max,
+ *                                 r_min, r_max.
+ * v0: device complex64, D entries, not modified (any nonzero vector; the
+ * tests draw a seeded complex Gaussian).  1 <= m <= min(D, 256).
+ * alpha_out, beta_out (HOST, m doubles each, may be NULL) receive the
+ * recurrence coefficients; steps_out (may be NULL) the step count, which is
+ * below m only if some beta_j is exactly zero.  Requires a plan.  Workspace
+ * (3 D complex64 + (1024 + 2m) doubles) is allocated on first use and kept
+ * with H.  SYNCHRONISES the stream.  PROCMV_ERR_INVALID_ARG for a null v0 or
+ * bounds_out or m out of range; PROCMV_ERR_INTERNAL if a coefficient is not
+ * finite (v0 zero or not finite). */
+procmv_status procmv_lanczos_bounds(procmv_op_t H, const void* v0, int32_t m,
+                                    double* bounds_out, double* alpha_out,
+                                    double* beta_out, int32_t* steps_out, void* stream);
+
 /* Chebyshev order for argument x = R dt and coefficient tolerance tol: the
  * first k >= x with 2|J_k(x)| < tol and 2|J_{k+1}(x)| < tol. */
 int32_t procmv_cheb_order(double x, double tol);

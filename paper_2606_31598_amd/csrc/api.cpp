@@ -86,6 +86,10 @@ struct procmv_op {
     size_t acc_bytes = 0;
     double* d_norm = nullptr;
     size_t norm_bytes = 0;
+    float2* d_lz = nullptr;     // Lanczos vectors v_prev, v, w (D each)
+    size_t lz_bytes = 0;
+    double* d_lzs = nullptr;    // Lanczos partials (2 x kLanczosMaxBlocks), alpha, beta
+    size_t lzs_bytes = 0;
     // measurement: event pairs around sampled launches
     int32_t prof_every = 0;
     int64_t prof_count[2] = {0, 0};
@@ -132,6 +136,8 @@ struct procmv_op {
         dfree(d_q);
         dfree(d_acc);
         dfree(d_norm);
+        dfree(d_lz);
+        dfree(d_lzs);
         for (int k = 0; k < 2; ++k)
             for (hipEvent_t e : prof_ev[k]) (void)hipEventDestroy(e);
     }
@@ -627,6 +633,132 @@ procmv_status procmv_spectral_bounds(procmv_op_t H, double* c, double* R)
         *c = 0.5 * (e_max + e_min);
         *R = 0.5 * (e_max - e_min);
     }
+    return PROCMV_OK;
+}
+
+namespace {
+
+// Eigenvalues and eigenvectors of the symmetric tridiagonal T (diagonal a,
+// off-diagonal b) by cyclic Jacobi rotations on a dense copy (Golub & Van
+// Loan, symmetric Schur decomposition; m is small).  Returns the extreme
+// eigenvalues and the last entries of their unit eigenvectors.
+void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b, int n,
+                      double& th_min, double& s_min, double& th_max, double& s_max)
+{
+    std::vector<double> A((size_t)n * n, 0.0), V((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        A[(size_t)i * n + i] = a[i];
+        V[(size_t)i * n + i] = 1.0;
+        if (i + 1 < n) A[(size_t)i * n + i + 1] = A[(size_t)(i + 1) * n + i] = b[i];
+    }
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double x = A[(size_t)i * n + j] * A[(size_t)i * n + j];
+                tot += x;
+                if (i != j) off += x;
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[(size_t)p * n + q];
+                if (apq == 0.0) continue;
+                const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                const double tau = (aqq - app) / (2.0 * apq);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) /
+                                 (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+                // A <- J^T A J with J the rotation in the (p, q) plane
+                for (int k = 0; k < n; ++k) {
+                    const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = c * akp - sn * akq;
+                    A[(size_t)k * n + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = c * apk - sn * aqk;
+                    A[(size_t)q * n + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = c * vkp - sn * vkq;
+                    V[(size_t)k * n + q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    int imin = 0, imax = 0;
+    for (int i = 1; i < n; ++i) {
+        if (A[(size_t)i * n + i] < A[(size_t)imin * n + imin]) imin = i;
+        if (A[(size_t)i * n + i] > A[(size_t)imax * n + imax]) imax = i;
+    }
+    th_min = A[(size_t)imin * n + imin];
+    th_max = A[(size_t)imax * n + imax];
+    s_min = V[(size_t)(n - 1) * n + imin];
+    s_max = V[(size_t)(n - 1) * n + imax];
+}
+
+}  // namespace
+
+procmv_status procmv_lanczos_bounds(procmv_op_t H, const void* v0, int32_t m,
+                                    double* bounds_out, double* alpha_out,
+                                    double* beta_out, int32_t* steps_out, void* stream)
+{
+    procmv_status st = check_op(H);
+    if (st != PROCMV_OK) return st;
+    if (!H->planned) return fail(PROCMV_ERR_NOT_PLANNED, "Lanczos before procmv_plan");
+    if (!v0 || !bounds_out) return fail(PROCMV_ERR_INVALID_ARG, "null v0 or bounds_out");
+    if (m < 1 || m > PROCMV_LANCZOS_MAX_STEPS || m > H->D)
+        return fail(PROCMV_ERR_INVALID_ARG, "m = %d outside [1, min(D, %d)]", m,
+                    PROCMV_LANCZOS_MAX_STEPS);
+    const int32_t D = (int32_t)H->D;
+    st = ensure(H->d_lz, H->lz_bytes, (size_t)3 * D * sizeof(float2));
+    if (st != PROCMV_OK) return st;
+    st = ensure(H->d_lzs, H->lzs_bytes,
+                (size_t)(2 * kLanczosMaxBlocks + 2 * m) * sizeof(double));
+    if (st != PROCMV_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    float2* vp = H->d_lz;
+    float2* v = H->d_lz + D;
+    float2* w = H->d_lz + 2 * (size_t)D;
+    double* dotp = H->d_lzs;
+    double* nrmp = H->d_lzs + kLanczosMaxBlocks;
+    double* d_alpha = H->d_lzs + 2 * kLanczosMaxBlocks;
+    double* d_beta = d_alpha + m;
+    // v_1 = v0 / ||v0||
+    HIP_TRY(launch_lanczos_normalise(D, (const float2*)v0, v, nrmp, nullptr, s));
+    for (int j = 0; j < m; ++j) {
+        st = procmv_apply(H, v, D, w, D, 1, stream);
+        if (st != PROCMV_OK) return st;
+        HIP_TRY(launch_lanczos_orthogonalise(D, v, vp, w, dotp, nrmp,
+                                             j > 0 ? d_beta + j - 1 : nullptr, d_alpha + j, s));
+        // v_{j+1} = w / beta_j overwrites v_{j-1}
+        HIP_TRY(launch_lanczos_normalise(D, w, vp, nrmp, d_beta + j, s));
+        std::swap(vp, v);
+    }
+    std::vector<double> a(m), b(m);
+    HIP_TRY(hipMemcpyAsync(a.data(), d_alpha, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(b.data(), d_beta, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    // an exactly invariant Krylov space ends the recurrence (later steps divided by zero)
+    int n = m;
+    for (int j = 0; j < m; ++j)
+        if (!(b[j] > 0.0)) { n = j + 1; b[j] = 0.0; break; }
+    for (int j = 0; j < n; ++j)
+        if (!std::isfinite(a[j]) || !std::isfinite(b[j]))
+            return fail(PROCMV_ERR_INTERNAL, "Lanczos step %d is not finite", j);
+    double th_min, s_min, th_max, s_max;
+    tridiag_extremes(a, b, n, th_min, s_min, th_max, s_max);
+    const double r_min = std::fabs(b[n - 1] * s_min), r_max = std::fabs(b[n - 1] * s_max);
+    bounds_out[0] = th_min - r_min;
+    bounds_out[1] = th_max + r_max;
+    bounds_out[2] = th_min;
+    bounds_out[3] = th_max;
+    bounds_out[4] = r_min;
+    bounds_out[5] = r_max;
+    if (alpha_out) for (int j = 0; j < n; ++j) alpha_out[j] = a[j];
+    if (beta_out) for (int j = 0; j < n; ++j) beta_out[j] = b[j];
+    if (steps_out) *steps_out = n;
     return PROCMV_OK;
 }
 

@@ -223,5 +223,18 @@ hipError_t launch_cheb_finish(int32_t D, int32_t nv, const double2* acc,
 hipError_t launch_copy_vectors(int32_t D, int32_t nv, const float2* src,
                                int64_t lds, float2* dst, int64_t ldd,
                                hipStream_t s);
+// Lanczos vector steps (defined in lanczos.hip).  Partial buffers hold
+// lanczos_blocks(D) <= kLanczosMaxBlocks doubles each.
+constexpr int32_t kLanczosMaxBlocks = 512;
+int32_t lanczos_blocks(int32_t D);
+// out = x / ||x|| (binary64 norm, stored in *norm_out when not null).
+hipError_t launch_lanczos_normalise(int32_t D, const float2* x, float2* out,
+                                    double* partials, double* norm_out, hipStream_t s);
+// *alpha_out = Re <v, w>; w <- w - alpha v - (*beta_prev) v_prev (beta_prev
+// null: no v_prev term); norm_partials <- partials of ||w||^2.
+hipError_t launch_lanczos_orthogonalise(int32_t D, const float2* v, const float2* v_prev,
+                                        float2* w, double* dot_partials,
+                                        double* norm_partials, const double* beta_prev,
+                                        double* alpha_out, hipStream_t s);
 
 }  // namespace procmv

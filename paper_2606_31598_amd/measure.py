@@ -168,15 +168,37 @@ def modes(reps, family="gue", D=32768):
         torch.cuda.synchronize()
 
 
+def lanczos(reps, m=40):
+    """Lanczos spectral bounds (m steps) against m plain products, on the
+    benchmark's operator and the small GUE one."""
+    torch = _cuda()
+    from . import procmv as pm, workloads
+    for name, D in (("dvr", 32768), ("gue", 2048), ("gue", 32768)):
+        op = pm.Operator.gue(D, seed=1) if name == "gue" else pm.Operator.dvr(D)
+        op.plan(256)
+        X = torch.from_numpy(workloads.gaussian_vectors(D, 1, seed=2).astype(np.complex64)).cuda()
+        Y = torch.empty_like(X)
+        t_l = _time(lambda: op.lanczos_bounds(X, m), reps, torch)
+        t_p = _time(lambda: op.apply(X, Y), reps * m, torch)
+        b = op.lanczos_bounds(X, m)
+        _emit({"config": "lanczos", "workload": f"{name} D={D} b=256 procedural, m={m}",
+               "ms_per_call": t_l * 1e3, "ms_m_products": t_p * m * 1e3,
+               "overhead": t_l / (t_p * m) - 1.0, "e_min": b["e_min"], "e_max": b["e_max"]})
+        op.close()
+        torch.cuda.synchronize()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["c0", "c2", "c3", "modes"])
+    ap.add_argument("cmd", choices=["c0", "c2", "c3", "modes", "lanczos"])
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--family", choices=["gue", "dvr"], default="gue")
     ap.add_argument("--D", type=int, default=32768)
     args = ap.parse_args(argv)
     if args.cmd == "modes":
         modes(args.reps, args.family, args.D)
+    elif args.cmd == "lanczos":
+        lanczos(args.reps)
     else:
         {"c0": c0, "c2": c2, "c3": c3}[args.cmd](args.reps)
 

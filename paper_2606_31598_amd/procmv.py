@@ -22,7 +22,7 @@ _STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "INFEASIBLE_PLAN",
 
 EXPORTS = [
     "procmv_create_operator", "procmv_plan", "procmv_apply",
-    "procmv_spectral_bounds", "procmv_cheb_order",
+    "procmv_spectral_bounds", "procmv_lanczos_bounds", "procmv_cheb_order",
     "procmv_chebyshev_propagate", "procmv_get_entries", "procmv_selftest_generator",
     "procmv_plan_info",
     "procmv_destroy", "procmv_last_error", "procmv_profile_enable",
@@ -83,6 +83,9 @@ def load():
     L.procmv_spectral_bounds.argtypes = [vp, c.POINTER(c.c_double),
                                          c.POINTER(c.c_double)]
     L.procmv_cheb_order.argtypes = [c.c_double, c.c_double]
+    L.procmv_lanczos_bounds.argtypes = [vp, vp, c.c_int32, c.POINTER(c.c_double),
+                                        c.POINTER(c.c_double), c.POINTER(c.c_double),
+                                        c.POINTER(c.c_int32), vp]
     L.procmv_cheb_order.restype = c.c_int32
     L.procmv_chebyshev_propagate.argtypes = [vp, vp, c.c_int64, c.c_int32,
                                              c.c_double, c.c_int32, c.c_int32,
@@ -365,6 +368,27 @@ class Operator:
         R = ctypes.c_double()
         _check(load().procmv_spectral_bounds(self._h, ctypes.byref(c), ctypes.byref(R)))
         return c.value, R.value
+
+    def lanczos_bounds(self, v0, m=40, stream=None):
+        """Matrix-free Lanczos spectral bounds from the start vector ``v0``
+        (complex64 CUDA tensor of D entries): dict with E_min, E_max, the
+        extreme Ritz values, their residual estimates, c, R and the recurrence
+        coefficients (binary64)."""
+        pp, _, nv = _vec_arg(v0, self.D)
+        if nv != 1:
+            raise ValueError("one start vector")
+        out = np.zeros(6, np.float64)
+        al = np.zeros(max(int(m), 1), np.float64)
+        be = np.zeros(max(int(m), 1), np.float64)
+        n = ctypes.c_int32()
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(load().procmv_lanczos_bounds(
+            self._h, pp, int(m), out.ctypes.data_as(dp), al.ctypes.data_as(dp),
+            be.ctypes.data_as(dp), ctypes.byref(n), _stream(stream)))
+        k = n.value
+        return {"e_min": out[0], "e_max": out[1], "theta_min": out[2], "theta_max": out[3],
+                "r_min": out[4], "r_max": out[5], "c": 0.5 * (out[1] + out[0]),
+                "R": 0.5 * (out[1] - out[0]), "steps": k, "alpha": al[:k], "beta": be[:k]}
 
     def propagate(self, psi, dt, nsteps=1, K=0, c=0.0, R=0.0, norms=False,
                   stream=None):

@@ -1,0 +1,107 @@
+"""GPU parity: matrix-free Lanczos spectral bounds against the binary64 oracle
+(paper Sec. VII: Lanczos estimates E_min, E_max before the Chebyshev
+propagation).
+
+Both sides run the same recurrence from the same complex64 start vector on the
+same binary32 generated entries; the library keeps its vectors in binary32
+with binary64 inner products and norms, the oracle runs in binary64.
+Tolerances (relative to the half-width R): a CPU model of the library's
+arithmetic (binary32 products and vectors, binary64 sums) differs from the
+binary64 recurrence by at most 6e-7 R in alpha/beta over 40 steps and 2.5e-8 R
+in the extreme Ritz values and bounds, at the sizes below; the tests allow
+1e-5 R and 1e-6 R.
+"""
+import numpy as np
+import pytest
+
+from oracle import lanczos as ol
+from paper_2606_31598_amd import workloads
+from tests.gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_COEF = 1e-5
+TOL_BOUND = 1e-6
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_31598_amd import procmv
+    procmv.load()
+    return procmv
+
+
+def _compare(got, ref, m):
+    R = ref["R"]
+    assert got["steps"] == ref["steps"] == m
+    assert np.max(np.abs(got["alpha"] - ref["alpha"])) <= TOL_COEF * R
+    assert np.max(np.abs(got["beta"] - ref["beta"])) <= TOL_COEF * R
+    for k in ("theta_min", "theta_max", "e_min", "e_max"):
+        assert abs(got[k] - ref[k]) <= TOL_BOUND * R, (k, got[k], ref[k])
+    assert abs(got["R"] - R) <= 2 * TOL_BOUND * R and abs(got["c"] - ref["c"]) <= 2 * TOL_BOUND * R
+
+
+def _v0(D, seed):
+    return workloads.gaussian_vectors(D, 1, seed)[0].astype(np.complex64)
+
+
+@pytest.mark.parametrize("D,b,strategy,frac", [(2048, 256, 0, 0.0), (700, 128, 1, 0.5),
+                                               (1000, 256, 2, 1.0)])
+def test_gue_lanczos_matches_oracle(pm, orc, D, b, strategy, frac):
+    m = 40
+    op = pm.Operator.gue(D, seed=1).plan(b, strategy, frac)
+    v0 = _v0(D, 2)
+    got = op.lanczos_bounds(to_dev(v0), m)
+    H = orc.gue_dense(1, D)
+    ref = ol.spectral_bounds(lambda v: H @ v, v0.astype(np.complex128), m)
+    print(f"GUE D={D}: dtheta_max/R = {abs(got['theta_max'] - ref['theta_max']) / ref['R']:.2e}")
+    _compare(got, ref, m)
+
+
+def test_dvr_lanczos_matches_oracle(pm, orc):
+    D, m = 4096, 40
+    op = pm.Operator.dvr(D).plan(256)
+    v0 = _v0(D, 3)
+    got = op.lanczos_bounds(to_dev(v0), m)
+    d = orc.DVR(D)
+    ref = ol.spectral_bounds(lambda v: d.apply_rows(v)[0], v0.astype(np.complex128), m)
+    _compare(got, ref, m)
+    # the top converges within 40 steps and the widened bound stays under the
+    # analytic one
+    assert got["e_max"] <= d.spectral_bounds()[1] * (1 + 1e-6)
+
+
+def test_full_krylov_space_ragged_block(pm, orc):
+    """m = D = 24 inside one ragged block: the Ritz values are the spectrum."""
+    D = 24
+    op = pm.Operator.gue(D, seed=9).plan(256)
+    got = op.lanczos_bounds(to_dev(_v0(D, 4)), D)
+    lam = np.linalg.eigvalsh(orc.gue_dense(9, D))
+    R = 0.5 * (lam[-1] - lam[0])
+    assert abs(got["theta_min"] - lam[0]) <= 1e-5 * R
+    assert abs(got["theta_max"] - lam[-1]) <= 1e-5 * R
+
+
+def test_bench_workload_lanczos(pm, orc):
+    """The benchmark's operator (sinc-DVR D = 32768, procedural b = 256), m = 40."""
+    D, m = 32768, 40
+    op = pm.Operator.dvr(D).plan(256)
+    v0 = _v0(D, 5)
+    got = op.lanczos_bounds(to_dev(v0), m)
+    d = orc.DVR(D)
+    ref = ol.spectral_bounds(lambda v: d.apply_rows(v)[0], v0.astype(np.complex128), m)
+    _compare(got, ref, m)
+
+
+def test_lanczos_rejects_bad_arguments(pm):
+    op = pm.Operator.gue(64, seed=1)
+    v = to_dev(_v0(64, 1))
+    with pytest.raises(pm.ProcmvError):
+        op.lanczos_bounds(v, 8)                  # no plan yet
+    op.plan(64)
+    for m in (0, 65, 257):
+        with pytest.raises(pm.ProcmvError):
+            op.lanczos_bounds(v, m)
