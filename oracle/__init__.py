@@ -15,6 +15,9 @@ Contents
   cross-checks);
 * Chebyshev propagation (``oracle.chebyshev``; paper Sec. VII, centered
   Chebyshev recurrence);
+* the imaginary-time Chebyshev filter e^{-tau H} (``oracle.chebyshev``;
+  paper Sec. I and VII, TPQ filtering);
+* matrix-free Lanczos spectral bounds (``oracle.lanczos``; paper Sec. VII);
 * planner formulas and the MLP surrogate in binary64 (``oracle.planner``;
   paper Sec. IV).
 """

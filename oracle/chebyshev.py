@@ -118,3 +118,63 @@ def exact_propagator(H: np.ndarray, t: float) -> np.ndarray:
     """exp(-i H t) from the eigendecomposition of a Hermitian matrix."""
     w, V = np.linalg.eigh(H)
     return (V * np.exp(-1j * w * t)) @ V.conj().T
+
+
+# --------------------------------------------------------------------------
+# Imaginary-time filter (paper Sec. I and Sec. VII: TPQ states are random
+# vectors filtered by a Chebyshev expansion of e^{-beta H/2}).  The paper does
+# not print its coefficients; they follow from the generating function
+# e^{z cos(theta)} = I_0(z) + 2 sum_k I_k(z) cos(k theta) with theta -> theta + pi:
+#   e^{-tau (c + R x)} = e^{-tau c} [I_0(z) + 2 sum_k (-1)^k I_k(z) T_k(x)],
+# z = R tau, written with the scaled e^{-z} I_k(z) and the factor e^{-tau (c - R)}.
+# --------------------------------------------------------------------------
+def bessel_i_scaled_seq(z: float, kmax: int) -> np.ndarray:
+    """e^{-z} I_k(z), k = 0..kmax, z >= 0, by Miller's backward recurrence
+    I_{k-1} = (2k/z) I_k + I_{k+1}, normalised by e^{-z} (I_0 + 2 sum I_k) = 1."""
+    if z == 0.0:
+        out = np.zeros(kmax + 1)
+        out[0] = 1.0
+        return out
+    top = max(kmax, int(math.sqrt(80.0 * max(z, 1.0))) + 40) + 30
+    v = np.zeros(top + 2)
+    v[top] = 1e-300
+    for k in range(top, 0, -1):
+        v[k - 1] = (2.0 * k / z) * v[k] + v[k + 1]
+        if v[k - 1] > 1e250:
+            v[k - 1:] *= 1e-250
+    norm = v[0] + 2.0 * v[1:].sum()
+    return v[: kmax + 1] / norm
+
+
+def filter_order(z: float, tol: float = 1e-10) -> int:
+    """First k (>= 1) with 2 e^{-z} I_k(z) < tol and 2 e^{-z} I_{k+1}(z) < tol."""
+    kmax = int(math.sqrt(80.0 * max(z, 1.0))) + 60
+    v = bessel_i_scaled_seq(z, kmax + 1)
+    for k in range(kmax + 1):
+        if 2.0 * v[k] < tol and 2.0 * v[k + 1] < tol:
+            return max(k, 1)
+    raise RuntimeError("order search ran past the table")
+
+
+def imag_time_filter(apply_h, psi, c: float, R: float, tau: float, K: int):
+    """e^{-tau H} psi (not normalised) by the Chebyshev expansion above;
+    ``apply_h(v)`` returns H v in binary64 for v of shape (nvec, D)."""
+    z = R * tau
+    iv = bessel_i_scaled_seq(z, K)
+    a = 2.0 * iv * np.where(np.arange(K + 1) % 2 == 1, -1.0, 1.0)
+    a[0] = iv[0]
+    psi = np.array(psi, dtype=np.complex128, copy=True)
+
+    def ht(v):
+        return (apply_h(v) - c * v) / R
+
+    q0 = psi
+    acc = a[0] * q0
+    if K >= 1:
+        q1 = ht(q0)
+        acc = acc + a[1] * q1
+        for k in range(2, K + 1):
+            q2 = 2.0 * ht(q1) - q0
+            acc = acc + a[k] * q2
+            q0, q1 = q1, q2
+    return math.exp(-tau * (c - R)) * acc
