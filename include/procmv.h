@@ -164,6 +164,30 @@ procmv_status procmv_chebyshev_propagate(procmv_op_t H, void* psi, int64_t ld,
                                          double spec_R, double* norms_out,
                                          void* stream);
 
+/* Chebyshev order of the imaginary-time filter for z = R tau: the first k
+ * with 2 e^{-z} I_k(z) < tol and 2 e^{-z} I_{k+1}(z) < tol (at least 1);
+ * -1 for z < 0 or tol <= 0. */
+int32_t procmv_filter_order(double z, double tol);
+
+/* Imaginary-time Chebyshev filter psi <- exp(-tau H) psi (paper Sec. I/VII:
+ * the TPQ states are prepared by an imaginary-time Chebyshev filter
+ * e^{-beta H/2} applied to random vectors; here tau = beta/2).  Same
+ * recurrence as procmv_chebyshev_propagate (Ht = (H - c)/R, q_0 = psi,
+ * q_1 = Ht q_0, q_{l+1} = 2 Ht q_l - q_{l-1}) with the coefficients of
+ * e^{-z x} = I_0(z) + 2 sum_k (-1)^k I_k(z) T_k(x), z = R tau, used in the
+ * exponentially scaled form e^{-z} I_k(z) with the factor
+ * e^{-tau (c - R)} = e^{-tau E_min} applied once at the end; binary64
+ * accumulation.  The result is NOT normalised: norms_out (HOST, may be NULL)
+ * receives the nvec binary64 norms ||exp(-tau H) psi||, and SYNCHRONISES
+ * the stream when given.  K <= 0: procmv_filter_order(R tau, 1e-10).
+ * spec_R <= 0 selects procmv_spectral_bounds (c, R must enclose the spectrum,
+ * or the expansion grows).  psi: device complex64 (nvec, ld), in place.
+ * PROCMV_ERR_INVALID_ARG for bad sizes, tau < 0, or a factor e^{-tau E_min}
+ * that overflows or underflows binary64. */
+procmv_status procmv_chebyshev_filter(procmv_op_t H, void* psi, int64_t ld, int32_t nvec,
+                                      double tau, int32_t K, double spec_c, double spec_R,
+                                      double* norms_out, void* stream);
+
 /* Test hook: the generated binary32 entries H[r0:r0+nr, c0:c0+nc] written to
  * out_dev (device, complex64, row-major nr x nc), through the same generator
  * code as the products.  Needs no plan. */

@@ -772,43 +772,17 @@ int32_t procmv_cheb_order(double x, double tol)
     return -1;
 }
 
-procmv_status procmv_chebyshev_propagate(procmv_op_t H, void* psi, int64_t ld,
-                                         int32_t nvec, double dt, int32_t K,
-                                         int32_t nsteps, double spec_c,
-                                         double spec_R, double* norms_out,
-                                         void* stream)
-{
-    procmv_status st = check_op(H);
-    if (st != PROCMV_OK) return st;
-    if (!H->planned) return fail(PROCMV_ERR_NOT_PLANNED, "propagation before procmv_plan");
-    if (!psi) return fail(PROCMV_ERR_INVALID_ARG, "psi is null");
-    if (nvec < 1 || nsteps < 0 || ld < H->D || !(dt >= 0.0))
-        return fail(PROCMV_ERR_INVALID_ARG, "bad nvec/nsteps/ld/dt");
-    double c = spec_c, R = spec_R;
-    if (!(R > 0.0)) {
-        st = procmv_spectral_bounds(H, &c, &R);
-        if (st != PROCMV_OK) return st;
-    }
-    // 1/R exact in binary32: the half-width is widened to 1/alpha.
-    const float alpha = f32_down(1.0 / R);
-    const double Reff = 1.0 / (double)alpha;
-    if (K <= 0) K = procmv_cheb_order(Reff * dt, 1e-10);
-    if (K < 1) return fail(PROCMV_ERR_INVALID_ARG, "Chebyshev order could not be set");
-    const std::vector<double> j = bessel_j(Reff * dt, K);
-    std::vector<double2> a(K + 1);
-    for (int k = 0; k <= K; ++k) {
-        const double m = (k == 0 ? 1.0 : 2.0) * j[k];
-        // (-i)^k
-        const int q = k & 3;
-        a[k] = q == 0 ? double2{m, 0.0} : q == 1 ? double2{0.0, -m}
-             : q == 2 ? double2{-m, 0.0} : double2{0.0, m};
-    }
-    const double2 phase{std::cos(c * dt), -std::sin(c * dt)};
-    const double dconst = H->gen == 1 ? H->d_const : 0.0;
-    float bhi, blo;
-    split_f32((double)alpha * (dconst - c), bhi, blo);
-    hipStream_t s = (hipStream_t)stream;
+namespace {
 
+// nsteps applications of psi <- phase * sum_k a_k T_k(Ht) psi, Ht = alpha (H - c)
+// (alpha (d - c) split into bhi + blo), in chunks of vectors; binary64 norms
+// after each step when norms_out is given (synchronises then).
+procmv_status cheb_run(procmv_op_t H, void* psi, int64_t ld, int32_t nvec, int32_t K,
+                       int32_t nsteps, const std::vector<double2>& a, double2 phase,
+                       float alpha, float bhi, float blo, double* norms_out, void* stream)
+{
+    procmv_status st = PROCMV_OK;
+    hipStream_t s = (hipStream_t)stream;
     for (int v0 = 0; v0 < nvec;) {
         const int nv = chunk_vectors(H, nvec - v0);
         float2* P0 = (float2*)psi + (size_t)v0 * ld;
@@ -872,6 +846,120 @@ procmv_status procmv_chebyshev_propagate(procmv_op_t H, void* psi, int64_t ld,
         v0 += nv;
     }
     return PROCMV_OK;
+}
+
+
+}  // namespace
+
+procmv_status procmv_chebyshev_propagate(procmv_op_t H, void* psi, int64_t ld,
+                                         int32_t nvec, double dt, int32_t K,
+                                         int32_t nsteps, double spec_c,
+                                         double spec_R, double* norms_out,
+                                         void* stream)
+{
+    procmv_status st = check_op(H);
+    if (st != PROCMV_OK) return st;
+    if (!H->planned) return fail(PROCMV_ERR_NOT_PLANNED, "propagation before procmv_plan");
+    if (!psi) return fail(PROCMV_ERR_INVALID_ARG, "psi is null");
+    if (nvec < 1 || nsteps < 0 || ld < H->D || !(dt >= 0.0))
+        return fail(PROCMV_ERR_INVALID_ARG, "bad nvec/nsteps/ld/dt");
+    double c = spec_c, R = spec_R;
+    if (!(R > 0.0)) {
+        st = procmv_spectral_bounds(H, &c, &R);
+        if (st != PROCMV_OK) return st;
+    }
+    // 1/R exact in binary32: the half-width is widened to 1/alpha.
+    const float alpha = f32_down(1.0 / R);
+    const double Reff = 1.0 / (double)alpha;
+    if (K <= 0) K = procmv_cheb_order(Reff * dt, 1e-10);
+    if (K < 1) return fail(PROCMV_ERR_INVALID_ARG, "Chebyshev order could not be set");
+    const std::vector<double> j = bessel_j(Reff * dt, K);
+    std::vector<double2> a(K + 1);
+    for (int k = 0; k <= K; ++k) {
+        const double m = (k == 0 ? 1.0 : 2.0) * j[k];
+        // (-i)^k
+        const int q = k & 3;
+        a[k] = q == 0 ? double2{m, 0.0} : q == 1 ? double2{0.0, -m}
+             : q == 2 ? double2{-m, 0.0} : double2{0.0, m};
+    }
+    const double2 phase{std::cos(c * dt), -std::sin(c * dt)};
+    const double dconst = H->gen == 1 ? H->d_const : 0.0;
+    float bhi, blo;
+    split_f32((double)alpha * (dconst - c), bhi, blo);
+    return cheb_run(H, psi, ld, nvec, K, nsteps, a, phase, alpha, bhi, blo, norms_out, stream);
+}
+
+namespace {
+
+// e^{-z} I_k(z), k = 0..kmax, z >= 0: Miller's backward recurrence
+// I_{k-1} = (2k/z) I_k + I_{k+1} from far above, normalised by the sum rule
+// e^{-z} (I_0 + 2 sum_{k>=1} I_k) = 1.
+std::vector<double> bessel_i_scaled(double z, int kmax)
+{
+    std::vector<double> out(kmax + 1, 0.0);
+    if (z == 0.0) {
+        out[0] = 1.0;
+        return out;
+    }
+    const int top = std::max(kmax, (int)std::sqrt(80.0 * std::max(z, 1.0)) + 40) + 30;
+    std::vector<double> v(top + 2, 0.0);
+    v[top] = 1e-300;
+    for (int k = top; k > 0; --k) {
+        v[k - 1] = (2.0 * k / z) * v[k] + v[k + 1];
+        if (v[k - 1] > 1e250)
+            for (int q = k - 1; q <= top; ++q) v[q] *= 1e-250;
+    }
+    double norm = v[0];
+    for (int k = 1; k <= top; ++k) norm += 2.0 * v[k];
+    for (int k = 0; k <= kmax; ++k) out[k] = v[k] / norm;
+    return out;
+}
+
+}  // namespace
+
+int32_t procmv_filter_order(double z, double tol)
+{
+    if (!(z >= 0.0) || !(tol > 0.0)) return -1;
+    const int kmax = (int)std::sqrt(80.0 * std::max(z, 1.0)) + 60;
+    const std::vector<double> v = bessel_i_scaled(z, kmax + 1);
+    for (int k = 0; k + 1 <= kmax + 1; ++k)
+        if (2.0 * v[k] < tol && 2.0 * v[k + 1] < tol) return std::max(k, 1);
+    return -1;
+}
+
+procmv_status procmv_chebyshev_filter(procmv_op_t H, void* psi, int64_t ld, int32_t nvec,
+                                      double tau, int32_t K, double spec_c, double spec_R,
+                                      double* norms_out, void* stream)
+{
+    procmv_status st = check_op(H);
+    if (st != PROCMV_OK) return st;
+    if (!H->planned) return fail(PROCMV_ERR_NOT_PLANNED, "filter before procmv_plan");
+    if (!psi) return fail(PROCMV_ERR_INVALID_ARG, "psi is null");
+    if (nvec < 1 || ld < H->D || !(tau >= 0.0))
+        return fail(PROCMV_ERR_INVALID_ARG, "bad nvec/ld/tau");
+    double c = spec_c, R = spec_R;
+    if (!(R > 0.0)) {
+        st = procmv_spectral_bounds(H, &c, &R);
+        if (st != PROCMV_OK) return st;
+    }
+    const float alpha = f32_down(1.0 / R);
+    const double Reff = 1.0 / (double)alpha;
+    const double z = Reff * tau;
+    if (K <= 0) K = procmv_filter_order(z, 1e-10);
+    if (K < 1) return fail(PROCMV_ERR_INVALID_ARG, "filter order could not be set");
+    // e^{-tau H} = e^{-tau (c - Reff)} sum_k (2 - delta_k0) (-1)^k e^{-z} I_k(z) T_k(Ht)
+    const std::vector<double> iv = bessel_i_scaled(z, K);
+    std::vector<double2> a(K + 1);
+    for (int k = 0; k <= K; ++k)
+        a[k] = double2{(k == 0 ? 1.0 : 2.0) * ((k & 1) ? -iv[k] : iv[k]), 0.0};
+    const double scale = std::exp(-tau * (c - Reff));
+    if (!std::isfinite(scale) || scale == 0.0)
+        return fail(PROCMV_ERR_INVALID_ARG, "e^{-tau (c - R)} = %g is out of range", scale);
+    const double2 phase{scale, 0.0};
+    const double dconst = H->gen == 1 ? H->d_const : 0.0;
+    float bhi, blo;
+    split_f32((double)alpha * (dconst - c), bhi, blo);
+    return cheb_run(H, psi, ld, nvec, K, 1, a, phase, alpha, bhi, blo, norms_out, stream);
 }
 
 procmv_status procmv_get_entries(procmv_op_t H, int64_t r0, int64_t c0,

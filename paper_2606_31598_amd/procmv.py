@@ -23,6 +23,7 @@ _STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "INFEASIBLE_PLAN",
 EXPORTS = [
     "procmv_create_operator", "procmv_plan", "procmv_apply",
     "procmv_spectral_bounds", "procmv_lanczos_bounds", "procmv_cheb_order",
+    "procmv_filter_order", "procmv_chebyshev_filter",
     "procmv_chebyshev_propagate", "procmv_get_entries", "procmv_selftest_generator",
     "procmv_plan_info",
     "procmv_destroy", "procmv_last_error", "procmv_profile_enable",
@@ -83,6 +84,11 @@ def load():
     L.procmv_spectral_bounds.argtypes = [vp, c.POINTER(c.c_double),
                                          c.POINTER(c.c_double)]
     L.procmv_cheb_order.argtypes = [c.c_double, c.c_double]
+    L.procmv_filter_order.argtypes = [c.c_double, c.c_double]
+    L.procmv_filter_order.restype = c.c_int32
+    L.procmv_chebyshev_filter.argtypes = [vp, vp, c.c_int64, c.c_int32, c.c_double,
+                                          c.c_int32, c.c_double, c.c_double,
+                                          c.POINTER(c.c_double), vp]
     L.procmv_lanczos_bounds.argtypes = [vp, vp, c.c_int32, c.POINTER(c.c_double),
                                         c.POINTER(c.c_double), c.POINTER(c.c_double),
                                         c.POINTER(c.c_int32), vp]
@@ -179,6 +185,10 @@ def _vec_arg(t, D):
 
 def cheb_order(x: float, tol: float = 1e-10) -> int:
     return int(load().procmv_cheb_order(float(x), float(tol)))
+
+
+def filter_order(z: float, tol: float = 1e-10) -> int:
+    return int(load().procmv_filter_order(float(z), float(tol)))
 
 
 def _f32(a):
@@ -389,6 +399,17 @@ class Operator:
         return {"e_min": out[0], "e_max": out[1], "theta_min": out[2], "theta_max": out[3],
                 "r_min": out[4], "r_max": out[5], "c": 0.5 * (out[1] + out[0]),
                 "R": 0.5 * (out[1] - out[0]), "steps": k, "alpha": al[:k], "beta": be[:k]}
+
+    def filter(self, psi, tau, K=0, c=0.0, R=0.0, norms=False, stream=None):
+        """psi <- exp(-tau H) psi in place (imaginary-time Chebyshev filter,
+        not normalised); returns the (nvec,) binary64 norms when ``norms``."""
+        pp, ld, nv = _vec_arg(psi, self.D)
+        out = np.zeros(nv, np.float64) if norms else None
+        optr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if norms else None
+        _check(load().procmv_chebyshev_filter(
+            self._h, pp, ld, nv, float(tau), int(K), float(c), float(R), optr,
+            _stream(stream)))
+        return out
 
     def propagate(self, psi, dt, nsteps=1, K=0, c=0.0, R=0.0, norms=False,
                   stream=None):

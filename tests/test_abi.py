@@ -97,3 +97,13 @@ def test_analytic_planner_prefers_cache_with_reuse():
     with _pt.raises(pm.ProcmvError) as e:
         pm.plan_choose(0, 262144, 64, 1e6, 1, 0, mm=mm)
     assert e.value.status == 3
+
+
+def test_filter_order_matches_oracle():
+    """Host-side order rule of the imaginary-time filter (no GPU needed)."""
+    from paper_2606_31598_amd import procmv
+    from oracle import chebyshev as ch
+    for z in (0.0, 0.5, 3.0, 40.0, 713.0 * 2.0, 5000.0):
+        for tol in (1e-7, 1e-10, 1e-13):
+            assert procmv.filter_order(z, tol) == ch.filter_order(z, tol)
+    assert procmv.filter_order(-1.0, 1e-10) == -1
