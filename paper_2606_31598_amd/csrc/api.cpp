@@ -732,8 +732,8 @@ procmv_status procmv_lanczos_bounds(procmv_op_t H, const void* v0, int32_t m,
         if (st != PROCMV_OK) return st;
         HIP_TRY(launch_lanczos_orthogonalise(D, v, vp, w, dotp, nrmp,
                                              j > 0 ? d_beta + j - 1 : nullptr, d_alpha + j, s));
-        // v_{j+1} = w / beta_j overwrites v_{j-1}
-        HIP_TRY(launch_lanczos_normalise(D, w, vp, nrmp, d_beta + j, s));
+        // v_{j+1} = w / beta_j overwrites v_{j-1} (the update wrote the norm partials)
+        HIP_TRY(launch_lanczos_scale(D, w, vp, nrmp, d_beta + j, s));
         std::swap(vp, v);
     }
     std::vector<double> a(m), b(m);

@@ -230,6 +230,10 @@ int32_t lanczos_blocks(int32_t D);
 // out = x / ||x|| (binary64 norm, stored in *norm_out when not null).
 hipError_t launch_lanczos_normalise(int32_t D, const float2* x, float2* out,
                                     double* partials, double* norm_out, hipStream_t s);
+// out = x / sqrt(sum of partials), the partials of ||x||^2 being already
+// written (by launch_lanczos_orthogonalise for the same x).
+hipError_t launch_lanczos_scale(int32_t D, const float2* x, float2* out,
+                                const double* partials, double* norm_out, hipStream_t s);
 // *alpha_out = Re <v, w>; w <- w - alpha v - (*beta_prev) v_prev (beta_prev
 // null: no v_prev term); norm_partials <- partials of ||w||^2.
 hipError_t launch_lanczos_orthogonalise(int32_t D, const float2* v, const float2* v_prev,

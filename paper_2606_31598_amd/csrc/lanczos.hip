@@ -128,6 +128,15 @@ hipError_t launch_lanczos_normalise(int32_t D, const float2* x, float2* out,
     return hipGetLastError();
 }
 
+hipError_t launch_lanczos_scale(int32_t D, const float2* x, float2* out,
+                                const double* partials, double* norm_out, hipStream_t s)
+{
+    const int g = lanczos_blocks(D);
+    hipLaunchKernelGGL(lz_scale_kernel, dim3(g), dim3(kLzThreads), 0, s, D, x, out, partials,
+                       g, norm_out);
+    return hipGetLastError();
+}
+
 hipError_t launch_lanczos_orthogonalise(int32_t D, const float2* v, const float2* v_prev,
                                         float2* w, double* dot_partials,
                                         double* norm_partials, const double* beta_prev,

@@ -188,9 +188,28 @@ def lanczos(reps, m=40):
         torch.cuda.synchronize()
 
 
+def filt(reps):
+    """Imaginary-time filter e^{-tau H} on one vector: time per call and per
+    Chebyshev term, automatic order (coefficient cut 1e-10)."""
+    torch = _cuda()
+    from . import procmv as pm, workloads
+    for name, D, tau in (("gue", 32768, 2.0), ("dvr", 32768, 0.01)):
+        op = pm.Operator.gue(D, seed=1) if name == "gue" else pm.Operator.dvr(D)
+        op.plan(256)
+        c, R = op.spectral_bounds()
+        K = pm.filter_order(R * tau, 1e-10)
+        X0 = torch.from_numpy(workloads.gaussian_vectors(D, 1, seed=2).astype(np.complex64)).cuda()
+        X = X0.clone()
+        t = _time(lambda: (X.copy_(X0), op.filter(X, tau, K=K)), reps, torch)
+        _emit({"config": "filter", "workload": f"{name} D={D} b=256 procedural, tau={tau}",
+               "K": K, "ms_per_filter": t * 1e3, "us_per_term": t / (K + 1) * 1e6})
+        op.close()
+        torch.cuda.synchronize()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["c0", "c2", "c3", "modes", "lanczos"])
+    ap.add_argument("cmd", choices=["c0", "c2", "c3", "modes", "lanczos", "filter"])
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--family", choices=["gue", "dvr"], default="gue")
     ap.add_argument("--D", type=int, default=32768)
@@ -199,6 +218,8 @@ def main(argv=None):
         modes(args.reps, args.family, args.D)
     elif args.cmd == "lanczos":
         lanczos(args.reps)
+    elif args.cmd == "filter":
+        filt(args.reps)
     else:
         {"c0": c0, "c2": c2, "c3": c3}[args.cmd](args.reps)
 
