@@ -18,6 +18,7 @@ Contents
 * the imaginary-time Chebyshev filter e^{-tau H} (``oracle.chebyshev``;
   paper Sec. I and VII, TPQ filtering);
 * matrix-free Lanczos spectral bounds (``oracle.lanczos``; paper Sec. VII);
+* the system-bath Kronecker operator (``oracle.kron``; paper Sec. VII example);
 * planner formulas and the MLP surrogate in binary64 (``oracle.planner``;
   paper Sec. IV).
 """

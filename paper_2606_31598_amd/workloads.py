@@ -68,3 +68,15 @@ def planner_workloads(n: int, seed: int, log2_d=(12, 18), nvec_max: int = 64,
         out.append({"D": 1 << k, "nvec": max(nv, 1), "budget_gb": bud,
                     "reuse": max(ru, 1), "family": fam})
     return out
+
+
+def system_matrices(d_s: int, n_int: int, seed: int) -> tuple:
+    """Synthetic system-side matrices of a system-bath operator: a Hermitian
+    H_S and n_int Hermitian couplings A_a, each (G + G^H)/2 of a complex
+    Gaussian G, rounded to complex64 values (returned as complex128)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(1 + n_int):
+        G = rng.standard_normal((d_s, d_s)) + 1j * rng.standard_normal((d_s, d_s))
+        out.append((0.5 * (G + G.conj().T)).astype(np.complex64).astype(np.complex128))
+    return out[0], out[1:]
