@@ -144,6 +144,29 @@ procmv_status procmv_lanczos_bounds(procmv_op_t H, const void* v0, int32_t m,
                                     double* bounds_out, double* alpha_out,
                                     double* beta_out, int32_t* steps_out, void* stream);
 
+/* Limits of procmv_kron_apply. */
+#define PROCMV_KRON_MAX_SYS 8
+#define PROCMV_KRON_MAX_INT 3
+
+/* System-bath Kronecker product Y = H X (paper Sec. VII example:
+ * H = H_S (x) I_B + I_S (x) H_B + g sum_a A_a (x) B_a, applied without forming
+ * H; Sec. IV-A: the bath operators act on R = d_S vectors at once).  X, Y:
+ * device complex64 of d_S * d_B entries, X[s * d_B + j] = component
+ * |s> (x) |j> (the d_S x d_B matrix, row-major); X and Y must not overlap.
+ * HB: the bath Hamiltonian, B[0..n_int): the interaction bath operators, all
+ * planned operators of the same D = d_B (any generator and plan; each product
+ * runs in its own plan's tile kernels, on the d_S rows of X).  HS (HOST,
+ * complex128 interleaved, d_S x d_S row-major) and A (HOST, n_int such
+ * matrices) are used as given (Hermitian for a Hermitian H) and rounded to
+ * binary32 in the mixing kernel.  1 <= d_S <= 8, 0 <= n_int <= 3.
+ * Workspace (1 + n_int) d_S d_B complex64 is allocated on first use and kept
+ * with HB.  Asynchronous on the stream.  PROCMV_ERR_INVALID_ARG for null
+ * pointers, sizes out of range, mismatched D or overlapping X and Y;
+ * PROCMV_ERR_NOT_PLANNED if an operator has no plan. */
+procmv_status procmv_kron_apply(procmv_op_t HB, const procmv_op_t* B, int32_t n_int,
+                                int32_t dS, const double* HS, const double* A, double g,
+                                const void* X, void* Y, void* stream);
+
 /* Chebyshev order for argument x = R dt and coefficient tolerance tol: the
  * first k >= x with 2|J_k(x)| < tol and 2|J_{k+1}(x)| < tol. */
 int32_t procmv_cheb_order(double x, double tol);

@@ -86,6 +86,8 @@ struct procmv_op {
     size_t acc_bytes = 0;
     double* d_norm = nullptr;
     size_t norm_bytes = 0;
+    float2* d_kz = nullptr;     // Kronecker bath products (1 + n_int) x d_S x D
+    size_t kz_bytes = 0;
     float2* d_lz = nullptr;     // Lanczos vectors v_prev, v, w (D each)
     size_t lz_bytes = 0;
     double* d_lzs = nullptr;    // Lanczos partials (2 x kLanczosMaxBlocks), alpha, beta
@@ -137,6 +139,7 @@ struct procmv_op {
         dfree(d_acc);
         dfree(d_norm);
         dfree(d_lz);
+        dfree(d_kz);
         dfree(d_lzs);
         for (int k = 0; k < 2; ++k)
             for (hipEvent_t e : prof_ev[k]) (void)hipEventDestroy(e);
@@ -759,6 +762,58 @@ procmv_status procmv_lanczos_bounds(procmv_op_t H, const void* v0, int32_t m,
     if (alpha_out) for (int j = 0; j < n; ++j) alpha_out[j] = a[j];
     if (beta_out) for (int j = 0; j < n; ++j) beta_out[j] = b[j];
     if (steps_out) *steps_out = n;
+    return PROCMV_OK;
+}
+
+procmv_status procmv_kron_apply(procmv_op_t HB, const procmv_op_t* B, int32_t n_int,
+                                int32_t dS, const double* HS, const double* A, double g,
+                                const void* X, void* Y, void* stream)
+{
+    procmv_status st = check_op(HB);
+    if (st != PROCMV_OK) return st;
+    if (dS < 1 || dS > PROCMV_KRON_MAX_SYS || n_int < 0 || n_int > PROCMV_KRON_MAX_INT)
+        return fail(PROCMV_ERR_INVALID_ARG, "d_S = %d or n_int = %d out of range", dS, n_int);
+    if (!HS || !X || !Y || (n_int > 0 && (!B || !A)))
+        return fail(PROCMV_ERR_INVALID_ARG, "null argument");
+    const int64_t dB = HB->D;
+    for (int a = 0; a < n_int; ++a) {
+        st = check_op(B[a]);
+        if (st != PROCMV_OK) return st;
+        if (B[a]->D != dB)
+            return fail(PROCMV_ERR_INVALID_ARG, "bath operator %d has D = %lld, H_B %lld", a,
+                        (long long)B[a]->D, (long long)dB);
+    }
+    const size_t vec = (size_t)dS * dB;
+    const char* xb = (const char*)X;
+    const char* yb = (const char*)Y;
+    if (xb < yb + vec * sizeof(float2) && yb < xb + vec * sizeof(float2))
+        return fail(PROCMV_ERR_INVALID_ARG, "X and Y overlap");
+    st = ensure(HB->d_kz, HB->kz_bytes, (size_t)(1 + n_int) * vec * sizeof(float2));
+    if (st != PROCMV_OK) return st;
+    // bath operators on the d_S rows of X (each checks its own plan)
+    st = procmv_apply(HB, X, dB, HB->d_kz, dB, dS, stream);
+    if (st != PROCMV_OK) return st;
+    for (int a = 0; a < n_int; ++a) {
+        st = procmv_apply(B[a], X, dB, HB->d_kz + (size_t)(1 + a) * vec, dB, dS, stream);
+        if (st != PROCMV_OK) return st;
+    }
+    KronMixArgs k{};
+    k.X = (const float2*)X;
+    k.Z = HB->d_kz;
+    k.Y = (float2*)Y;
+    k.dB = dB;
+    k.dS = dS;
+    k.n_int = n_int;
+    for (int op = 0; op <= n_int; ++op)
+        for (int s = 0; s < dS; ++s)
+            for (int t = 0; t < dS; ++t) {
+                const double* m = op == 0 ? HS + 2 * (s * dS + t)
+                                          : A + 2 * (((size_t)(op - 1) * dS + s) * dS + t);
+                const double f = op == 0 ? 1.0 : g;
+                k.M[(op * kKronMaxSys + s) * kKronMaxSys + t] =
+                    make_float2((float)(f * m[0]), (float)(f * m[1]));
+            }
+    HIP_TRY(launch_kron_mix(k, (hipStream_t)stream));
     return PROCMV_OK;
 }
 

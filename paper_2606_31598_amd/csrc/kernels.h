@@ -223,6 +223,20 @@ hipError_t launch_cheb_finish(int32_t D, int32_t nv, const double2* acc,
 hipError_t launch_copy_vectors(int32_t D, int32_t nv, const float2* src,
                                int64_t lds, float2* dst, int64_t ldd,
                                hipStream_t s);
+// System-side mixing of the system-bath Kronecker product (defined in kron.hip).
+constexpr int kKronMaxSys = 8;     // d_S
+constexpr int kKronMaxInt = 3;     // interaction terms
+struct KronMixArgs {
+    const float2* X;   // (dS, dB) input
+    const float2* Z;   // (1 + n_int, dS, dB) bath products: H_B rows, then B_a rows
+    float2* Y;         // (dS, dB) output
+    int64_t dB;
+    int32_t dS;
+    int32_t n_int;
+    // M_0 = H_S, M_a = g A_a, each kKronMaxSys x kKronMaxSys row-major (top-left dS x dS used)
+    float2 M[(1 + kKronMaxInt) * kKronMaxSys * kKronMaxSys];
+};
+hipError_t launch_kron_mix(const KronMixArgs& a, hipStream_t s);
 // Lanczos vector steps (defined in lanczos.hip).  Partial buffers hold
 // lanczos_blocks(D) <= kLanczosMaxBlocks doubles each.
 constexpr int32_t kLanczosMaxBlocks = 512;

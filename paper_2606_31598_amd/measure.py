@@ -207,9 +207,32 @@ def filt(reps):
         torch.cuda.synchronize()
 
 
+def kron(reps):
+    """System-bath Kronecker product at the paper's run shape: d_S = 4,
+    d_B = 65536, one interaction term (two procedural Philox-GUE bath
+    operators), block sizes 4096 (the paper's autotuned choice) and 256."""
+    torch = _cuda()
+    from . import procmv as pm, workloads
+    dS, dB = 4, 65536
+    HS, As = workloads.system_matrices(dS, 1, seed=3)
+    X = torch.from_numpy(workloads.gaussian_vectors(dS * dB, 1, seed=4)[0]
+                         .astype(np.complex64).reshape(dS, dB)).cuda()
+    Y = torch.empty_like(X)
+    flops = 2 * 8 * dS * dB * dB          # two bath operators, 8 flop per complex MAC
+    for b in (4096, 256):
+        HB = pm.Operator.gue(dB, seed=41).plan(b)
+        B = pm.Operator.gue(dB, seed=42).plan(b)
+        t = _time(lambda: pm.kron_apply(HB, [B], HS, As, 0.5, X, Y), reps, torch)
+        _emit({"config": "kron", "workload": f"system-bath d_S={dS} d_B={dB} n_int=1, b={b}",
+               "ms_per_apply": t * 1e3, "flop_per_apply": flops, "tflop_s": flops / t / 1e12})
+        HB.close()
+        B.close()
+        torch.cuda.synchronize()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["c0", "c2", "c3", "modes", "lanczos", "filter"])
+    ap.add_argument("cmd", choices=["c0", "c2", "c3", "modes", "lanczos", "filter", "kron"])
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--family", choices=["gue", "dvr"], default="gue")
     ap.add_argument("--D", type=int, default=32768)
@@ -220,6 +243,8 @@ def main(argv=None):
         lanczos(args.reps)
     elif args.cmd == "filter":
         filt(args.reps)
+    elif args.cmd == "kron":
+        kron(args.reps)
     else:
         {"c0": c0, "c2": c2, "c3": c3}[args.cmd](args.reps)
 
