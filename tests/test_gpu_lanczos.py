@@ -105,3 +105,12 @@ def test_lanczos_rejects_bad_arguments(pm):
     for m in (0, 65, 257):
         with pytest.raises(pm.ProcmvError):
             op.lanczos_bounds(v, m)
+
+
+def test_lanczos_zero_start_vector_is_an_error(pm):
+    """A zero start vector has no direction: the first coefficient is not
+    finite and the call reports it instead of returning bounds."""
+    import torch
+    op = pm.Operator.gue(256, seed=1).plan(128)
+    with pytest.raises(pm.ProcmvError):
+        op.lanczos_bounds(torch.zeros(256, dtype=torch.complex64, device="cuda"), 8)
