@@ -167,6 +167,27 @@ procmv_status procmv_kron_apply(procmv_op_t HB, const procmv_op_t* B, int32_t n_
                                 int32_t dS, const double* HS, const double* A, double g,
                                 const void* X, void* Y, void* stream);
 
+/* Real-time propagation of a system-bath state, psi <- exp(-i H dt)^nsteps
+ * psi, with H the operator of procmv_kron_apply (same arguments HB, B, n_int,
+ * d_S, HS, A, g) and the centered Chebyshev expansion of
+ * procmv_chebyshev_propagate (paper Sec. VII: the example propagates its
+ * system-bath state this way).  Every term is one procmv_kron_apply plus one
+ * vector kernel (q_{k+1} = 2 (H q_k - c q_k)/R - q_{k-1} in binary64, rounded
+ * to complex64; binary64 coefficient sum).  spec_c, spec_R: the caller's
+ * spectral centre and half-width (R > 0; they must enclose the spectrum, e.g.
+ * from procmv_lanczos_bounds-style estimates with a margin).  K <= 0:
+ * procmv_cheb_order(R dt, 1e-10).  psi: device complex64, d_S * d_B entries
+ * (layout of procmv_kron_apply), in place.  norms_out (HOST, may be NULL):
+ * nsteps binary64 norms, SYNCHRONISES the stream when given.  Workspace
+ * (2 d_S d_B complex64 + d_S d_B complex128) is kept with HB.
+ * PROCMV_ERR_INVALID_ARG as procmv_kron_apply, or for R <= 0, dt < 0,
+ * nsteps < 0 or d_S d_B >= 2^31. */
+procmv_status procmv_kron_propagate(procmv_op_t HB, const procmv_op_t* B, int32_t n_int,
+                                    int32_t dS, const double* HS, const double* A, double g,
+                                    void* psi, double dt, int32_t K, int32_t nsteps,
+                                    double spec_c, double spec_R, double* norms_out,
+                                    void* stream);
+
 /* Chebyshev order for argument x = R dt and coefficient tolerance tol: the
  * first k >= x with 2|J_k(x)| < tol and 2|J_{k+1}(x)| < tol. */
 int32_t procmv_cheb_order(double x, double tol);

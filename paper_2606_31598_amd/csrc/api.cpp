@@ -88,6 +88,10 @@ struct procmv_op {
     size_t norm_bytes = 0;
     float2* d_kz = nullptr;     // Kronecker bath products (1 + n_int) x d_S x D
     size_t kz_bytes = 0;
+    float2* d_kq = nullptr;     // Kronecker Chebyshev: q buffer and product (2 x d_S x D)
+    size_t kq_bytes = 0;
+    double2* d_kacc = nullptr;  // Kronecker Chebyshev accumulator (d_S x D) + norm
+    size_t kacc_bytes = 0;
     float2* d_lz = nullptr;     // Lanczos vectors v_prev, v, w (D each)
     size_t lz_bytes = 0;
     double* d_lzs = nullptr;    // Lanczos partials (2 x kLanczosMaxBlocks), alpha, beta
@@ -140,6 +144,8 @@ struct procmv_op {
         dfree(d_norm);
         dfree(d_lz);
         dfree(d_kz);
+        dfree(d_kq);
+        dfree(d_kacc);
         dfree(d_lzs);
         for (int k = 0; k < 2; ++k)
             for (hipEvent_t e : prof_ev[k]) (void)hipEventDestroy(e);
@@ -814,6 +820,66 @@ procmv_status procmv_kron_apply(procmv_op_t HB, const procmv_op_t* B, int32_t n_
                     make_float2((float)(f * m[0]), (float)(f * m[1]));
             }
     HIP_TRY(launch_kron_mix(k, (hipStream_t)stream));
+    return PROCMV_OK;
+}
+
+procmv_status procmv_kron_propagate(procmv_op_t HB, const procmv_op_t* B, int32_t n_int,
+                                    int32_t dS, const double* HS, const double* A, double g,
+                                    void* psi, double dt, int32_t K, int32_t nsteps,
+                                    double spec_c, double spec_R, double* norms_out,
+                                    void* stream)
+{
+    procmv_status st = check_op(HB);
+    if (st != PROCMV_OK) return st;
+    if (!psi) return fail(PROCMV_ERR_INVALID_ARG, "psi is null");
+    if (dS < 1 || dS > PROCMV_KRON_MAX_SYS || nsteps < 0 || !(dt >= 0.0) || !(spec_R > 0.0))
+        return fail(PROCMV_ERR_INVALID_ARG, "bad d_S/nsteps/dt/R");
+    const int64_t n = (int64_t)dS * HB->D;
+    if (n > INT32_MAX) return fail(PROCMV_ERR_INVALID_ARG, "d_S d_B too large");
+    if (K <= 0) K = procmv_cheb_order(spec_R * dt, 1e-10);
+    if (K < 1) return fail(PROCMV_ERR_INVALID_ARG, "Chebyshev order could not be set");
+    st = ensure(HB->d_kq, HB->kq_bytes, (size_t)2 * n * sizeof(float2));
+    if (st != PROCMV_OK) return st;
+    st = ensure(HB->d_kacc, HB->kacc_bytes, (size_t)(n + 1) * sizeof(double2));
+    if (st != PROCMV_OK) return st;
+    const std::vector<double> j = bessel_j(spec_R * dt, K);
+    std::vector<double2> a(K + 1);
+    for (int k = 0; k <= K; ++k) {
+        const double m = (k == 0 ? 1.0 : 2.0) * j[k];
+        const int q = k & 3;   // (-i)^k
+        a[k] = q == 0 ? double2{m, 0.0} : q == 1 ? double2{0.0, -m}
+             : q == 2 ? double2{-m, 0.0} : double2{0.0, m};
+    }
+    const double2 phase{std::cos(spec_c * dt), -std::sin(spec_c * dt)};
+    const double alpha = 1.0 / spec_R;
+    hipStream_t s = (hipStream_t)stream;
+    float2* P0 = (float2*)psi;
+    float2* qa = HB->d_kq;
+    float2* Yb = HB->d_kq + n;
+    double2* acc = HB->d_kacc;
+    double* norm2 = (double*)(HB->d_kacc + n);
+    for (int step = 0; step < nsteps; ++step) {
+        HIP_TRY(launch_kron_cheb_init(n, P0, acc, a[0], s));
+        st = procmv_kron_apply(HB, B, n_int, dS, HS, A, g, P0, Yb, stream);
+        if (st != PROCMV_OK) return st;
+        HIP_TRY(launch_kron_cheb_term(n, Yb, P0, qa, acc, alpha, spec_c, a[1], 1, s));
+        // q_0 lives in psi, q_1 in qa; each term overwrites the older one
+        float2* prev = P0;
+        float2* cur = qa;
+        for (int k = 1; k < K; ++k) {
+            st = procmv_kron_apply(HB, B, n_int, dS, HS, A, g, cur, Yb, stream);
+            if (st != PROCMV_OK) return st;
+            HIP_TRY(launch_kron_cheb_term(n, Yb, cur, prev, acc, alpha, spec_c, a[k + 1], 0, s));
+            std::swap(prev, cur);
+        }
+        HIP_TRY(launch_cheb_finish((int32_t)n, 1, acc, n, phase, P0, n, norm2, s));
+        if (norms_out) {
+            double v = 0.0;
+            HIP_TRY(hipMemcpyAsync(&v, norm2, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            norms_out[step] = std::sqrt(v);
+        }
+    }
     return PROCMV_OK;
 }
 

@@ -237,6 +237,14 @@ struct KronMixArgs {
     float2 M[(1 + kKronMaxInt) * kKronMaxSys * kKronMaxSys];
 };
 hipError_t launch_kron_mix(const KronMixArgs& a, hipStream_t s);
+// Chebyshev propagation of the system-bath operator (defined in kron.hip):
+// acc = coef q; and one term q_new = [2] alpha (Y - c q_k) [- q_prev] over
+// q_prev with acc += coef q_new (binary64).
+hipError_t launch_kron_cheb_init(int64_t n, const float2* q, double2* acc, double2 coef,
+                                 hipStream_t s);
+hipError_t launch_kron_cheb_term(int64_t n, const float2* Y, const float2* qk, float2* qprev,
+                                 double2* acc, double alpha, double c, double2 coef,
+                                 int first, hipStream_t s);
 // Lanczos vector steps (defined in lanczos.hip).  Partial buffers hold
 // lanczos_blocks(D) <= kLanczosMaxBlocks doubles each.
 constexpr int32_t kLanczosMaxBlocks = 512;

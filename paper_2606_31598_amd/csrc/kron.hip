@@ -61,3 +61,67 @@ hipError_t launch_kron_mix(const KronMixArgs& a, hipStream_t s)
 }
 
 }  // namespace procmv
+
+namespace procmv {
+
+namespace {
+
+// One Chebyshev term of the system-bath propagation (paper Sec. VII,
+// Ht = (H - c)/R): with Y = H q_k,
+//   first:  q_new = alpha (Y - c q_k)
+//   later:  q_new = 2 alpha (Y - c q_k) - q_prev
+// written over q_prev, and acc += coef q_new in binary64.
+__global__ __launch_bounds__(256) void kron_cheb_term_kernel(
+    int64_t n, const float2* __restrict__ Y, const float2* __restrict__ qk,
+    float2* __restrict__ qprev, double2* __restrict__ acc, double alpha, double c,
+    double2 coef, int first)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 y = Y[i], q = qk[i];
+    double rx = alpha * ((double)y.x - c * (double)q.x);
+    double ry = alpha * ((double)y.y - c * (double)q.y);
+    if (!first) {
+        const float2 p = qprev[i];
+        rx = 2.0 * rx - (double)p.x;
+        ry = 2.0 * ry - (double)p.y;
+    }
+    const float2 o = make_float2((float)rx, (float)ry);
+    qprev[i] = o;
+    double2 a = acc[i];
+    a.x += coef.x * (double)o.x - coef.y * (double)o.y;
+    a.y += coef.x * (double)o.y + coef.y * (double)o.x;
+    acc[i] = a;
+}
+
+// acc = coef q (start of a step).
+__global__ __launch_bounds__(256) void kron_cheb_init_kernel(
+    int64_t n, const float2* __restrict__ q, double2* __restrict__ acc, double2 coef)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 v = q[i];
+    acc[i] = double2{coef.x * (double)v.x - coef.y * (double)v.y,
+                     coef.x * (double)v.y + coef.y * (double)v.x};
+}
+
+}  // namespace
+
+hipError_t launch_kron_cheb_init(int64_t n, const float2* q, double2* acc, double2 coef,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL(kron_cheb_init_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       s, n, q, acc, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_kron_cheb_term(int64_t n, const float2* Y, const float2* qk, float2* qprev,
+                                 double2* acc, double alpha, double c, double2 coef,
+                                 int first, hipStream_t s)
+{
+    hipLaunchKernelGGL(kron_cheb_term_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       s, n, Y, qk, qprev, acc, alpha, c, coef, first);
+    return hipGetLastError();
+}
+
+}  // namespace procmv

@@ -23,7 +23,7 @@ _STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "INFEASIBLE_PLAN",
 EXPORTS = [
     "procmv_create_operator", "procmv_plan", "procmv_apply",
     "procmv_spectral_bounds", "procmv_lanczos_bounds", "procmv_cheb_order",
-    "procmv_filter_order", "procmv_chebyshev_filter", "procmv_kron_apply",
+    "procmv_filter_order", "procmv_chebyshev_filter", "procmv_kron_apply", "procmv_kron_propagate",
     "procmv_chebyshev_propagate", "procmv_get_entries", "procmv_selftest_generator",
     "procmv_plan_info",
     "procmv_destroy", "procmv_last_error", "procmv_profile_enable",
@@ -88,6 +88,10 @@ def load():
     L.procmv_kron_apply.argtypes = [vp, c.POINTER(vp), c.c_int32, c.c_int32,
                                     c.POINTER(c.c_double), c.POINTER(c.c_double), c.c_double,
                                     vp, vp, vp]
+    L.procmv_kron_propagate.argtypes = [vp, c.POINTER(vp), c.c_int32, c.c_int32,
+                                        c.POINTER(c.c_double), c.POINTER(c.c_double),
+                                        c.c_double, vp, c.c_double, c.c_int32, c.c_int32,
+                                        c.c_double, c.c_double, c.POINTER(c.c_double), vp]
     L.procmv_filter_order.restype = c.c_int32
     L.procmv_chebyshev_filter.argtypes = [vp, vp, c.c_int64, c.c_int32, c.c_double,
                                           c.c_int32, c.c_double, c.c_double,
@@ -190,29 +194,46 @@ def cheb_order(x: float, tol: float = 1e-10) -> int:
     return int(load().procmv_cheb_order(float(x), float(tol)))
 
 
+def _kron_args(HB, Bs, HS, As, tensors):
+    import torch
+    HS = np.ascontiguousarray(HS, np.complex128)
+    dS = HS.shape[0]
+    As = np.ascontiguousarray(np.asarray(As, np.complex128).reshape(-1, dS, dS))
+    if As.shape[0] != len(Bs):
+        raise ValueError("one A per bath operator")
+    for t in tensors:
+        if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous() \
+                or tuple(t.shape) != (dS, HB.D):
+            raise ValueError(f"state tensors must be contiguous complex64 CUDA ({dS}, {HB.D})")
+    handles = (ctypes.c_void_p * max(len(Bs), 1))(*[b._h.value for b in Bs])
+    dp = ctypes.POINTER(ctypes.c_double)
+    return (HB._h, ctypes.cast(handles, ctypes.POINTER(ctypes.c_void_p)), len(Bs), dS,
+            HS.view(np.float64).ctypes.data_as(dp),
+            As.view(np.float64).ctypes.data_as(dp) if len(Bs) else None), (HS, As, handles)
+
+
 def kron_apply(HB, Bs, HS, As, g, X, Y, stream=None):
     """Y = (H_S x I + I x H_B + g sum_a A_a x B_a) X for the (d_S, d_B)
     complex64 CUDA tensors X, Y (row s = system index s).  HB and Bs are
     planned Operators of the same D = d_B; HS (d_S, d_S) and As (n_int, d_S,
     d_S) are host complex matrices."""
-    import torch
-    HS = np.ascontiguousarray(HS, np.complex128)
-    dS = HS.shape[0]
-    As = np.ascontiguousarray(np.asarray(As, np.complex128).reshape(-1, dS, dS))
-    n_int = len(Bs)
-    if As.shape[0] != n_int:
-        raise ValueError("one A per bath operator")
-    for t in (X, Y):
-        if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous() \
-                or tuple(t.shape) != (dS, HB.D):
-            raise ValueError(f"X, Y must be contiguous complex64 CUDA ({dS}, {HB.D})")
-    handles = (ctypes.c_void_p * max(n_int, 1))(*[b._h.value for b in Bs])
-    dp = ctypes.POINTER(ctypes.c_double)
-    _check(load().procmv_kron_apply(
-        HB._h, ctypes.cast(handles, ctypes.POINTER(ctypes.c_void_p)), n_int, dS,
-        HS.view(np.float64).ctypes.data_as(dp),
-        As.view(np.float64).ctypes.data_as(dp) if n_int else None, float(g),
-        ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()), _stream(stream)))
+    args, keep = _kron_args(HB, Bs, HS, As, (X, Y))
+    _check(load().procmv_kron_apply(*args, float(g), ctypes.c_void_p(X.data_ptr()),
+                                    ctypes.c_void_p(Y.data_ptr()), _stream(stream)))
+
+
+def kron_propagate(HB, Bs, HS, As, g, psi, dt, nsteps, c, R, K=0, norms=False,
+                   stream=None):
+    """psi <- exp(-i H dt)^nsteps psi in place for the system-bath operator of
+    ``kron_apply`` (centered Chebyshev with centre c and half-width R);
+    returns the binary64 norm after each step when ``norms``."""
+    args, keep = _kron_args(HB, Bs, HS, As, (psi,))
+    out = np.zeros(max(int(nsteps), 1), np.float64) if norms else None
+    optr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if norms else None
+    _check(load().procmv_kron_propagate(*args, float(g), ctypes.c_void_p(psi.data_ptr()),
+                                        float(dt), int(K), int(nsteps), float(c), float(R),
+                                        optr, _stream(stream)))
+    return out
 
 
 def filter_order(z: float, tol: float = 1e-10) -> int:

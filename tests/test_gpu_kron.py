@@ -95,3 +95,26 @@ def test_kron_rejects_bad_arguments(pm):
         pm.kron_apply(HB, [HB], HS, As, 0.1, X, X)          # X and Y overlap
     with pytest.raises(pm.ProcmvError):
         pm.kron_apply(HB, [HB] * 4, HS, np.stack([As[0]] * 4), 0.1, X, Y)   # n_int > 3
+
+
+def test_kron_propagation_matches_oracle(pm):
+    """Real-time Chebyshev propagation of a system-bath state (the paper's
+    example workload) against the oracle's binary64 propagation with the same
+    centre, half-width and order; the norm is conserved."""
+    from oracle import chebyshev as ch
+    dS, dB, g, dt, steps = 2, 512, 0.3, 0.05, 10
+    HS, As = workloads.system_matrices(dS, 1, seed=12)
+    HB = pm.Operator.gue(dB, seed=51).plan(128)
+    B = pm.Operator.gue(dB, seed=52).plan(128, pm.FULL, 1.0)
+    # half-width from the norms: |H_S| + |H_B| + g |A| |B|, GUE radius below 2.5
+    R = (np.max(np.abs(np.linalg.eigvalsh(HS))) + 2.5
+         + abs(g) * np.max(np.abs(np.linalg.eigvalsh(As[0]))) * 2.5)
+    c = 0.0
+    psi0 = workloads.gaussian_vectors(dS * dB, 1, seed=13)[0].astype(np.complex64)
+    P = to_dev(psi0.reshape(dS, dB))
+    norms = pm.kron_propagate(HB, [B], HS, As, g, P, dt, steps, c, R, norms=True)
+    K = ch.cheb_order(R * dt)
+    apply_h = lambda v: ok.kron_apply(HS, _rows(51, dB), As, [_rows(52, dB)], g, v[0])[None]
+    ref = ch.propagate(apply_h, psi0[None].astype(np.complex128), c, R, dt, K, nsteps=steps)
+    assert rel_l2(to_host(P).reshape(-1), ref[0]) < 1e-5
+    assert np.max(np.abs(norms - 1.0)) < 1e-5
