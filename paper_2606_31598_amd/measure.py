@@ -209,8 +209,10 @@ def filt(reps):
 
 def kron(reps):
     """System-bath Kronecker product at the paper's run shape: d_S = 4,
-    d_B = 65536, one interaction term (two procedural Philox-GUE bath
-    operators), block sizes 4096 (the paper's autotuned choice) and 256."""
+    d_B = 65536, one interaction term (two Philox-GUE bath operators):
+    procedural at block sizes 4096 (the paper's autotuned choice) and 256, and
+    fully cached (34 GB of canonical blocks), with one 181-term Chebyshev
+    step on the cached operators."""
     torch = _cuda()
     from . import procmv as pm, workloads
     dS, dB = 4, 65536
@@ -219,12 +221,26 @@ def kron(reps):
                          .astype(np.complex64).reshape(dS, dB)).cuda()
     Y = torch.empty_like(X)
     flops = 2 * 8 * dS * dB * dB          # two bath operators, 8 flop per complex MAC
-    for b in (4096, 256):
-        HB = pm.Operator.gue(dB, seed=41).plan(b)
-        B = pm.Operator.gue(dB, seed=42).plan(b)
+    for b, strat, f in ((4096, pm.PROCEDURAL, 0.0), (256, pm.PROCEDURAL, 0.0),
+                        (256, pm.FULL, 1.0)):
+        HB = pm.Operator.gue(dB, seed=41).plan(b, strat, f)
+        B = pm.Operator.gue(dB, seed=42).plan(b, strat, f)
         t = _time(lambda: pm.kron_apply(HB, [B], HS, As, 0.5, X, Y), reps, torch)
-        _emit({"config": "kron", "workload": f"system-bath d_S={dS} d_B={dB} n_int=1, b={b}",
-               "ms_per_apply": t * 1e3, "flop_per_apply": flops, "tflop_s": flops / t / 1e12})
+        name = "procedural" if f == 0 else "full cache"
+        rec = {"config": "kron", "workload": f"system-bath d_S={dS} d_B={dB} n_int=1, b={b} {name}",
+               "cache_gb": (HB.plan_info()["cache_bytes"] + B.plan_info()["cache_bytes"]) / 1e9,
+               "ms_per_apply": t * 1e3, "flop_per_apply": flops, "tflop_s": flops / t / 1e12}
+        if f == 1.0:
+            # one real-time Chebyshev step at the paper's order (181 terms per step)
+            P = X.clone()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pm.kron_propagate(HB, [B], HS, As, 0.5, P, 0.01, 1, 0.0, 10.0, K=181)
+            e1.record()
+            torch.cuda.synchronize()
+            rec["cheb_step_K181_s"] = e0.elapsed_time(e1) / 1e3
+        _emit(rec)
         HB.close()
         B.close()
         torch.cuda.synchronize()
