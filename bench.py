@@ -4,15 +4,20 @@ Default workload: sinc-DVR harmonic oscillator, D = 32768 on x in [-20, 20],
 wavepacket at x0 = 3 (sigma = 1), Chebyshev propagation with dt = 0.05 and
 the order from the Bessel-coefficient rule.  One benchmark step is one
 Chebyshev time step: K + 1 coefficient terms, K products H q (each one
-generated-block product over all D^2 entries plus its fixed-order reduction
-with the recurrence and the binary64 accumulation fused), and the final
-rounding and binary64 norm.
+generated-block product over all D^2 entries, by default the matrix-core
+Toeplitz kernel, plus its fixed-order reduction with the recurrence and the
+binary64 accumulation fused), and the final rounding and binary64 norm.  The
+default arithmetic is the compensated binary32 one (band in difference form,
+hi + lo recurrence vectors), which keeps the state within 1e-4 sqrt(n/200)
+of the exact one; --precision fp32 gives the plain binary32 arithmetic.
 
 The JSON line reports the whole-step throughput in matrix elements applied
 per second, the throughput of each storage mode (procedural, 50% partial
 cache, full cache) for single products, the roofline position of the
 dominant kernel (from HIP events recorded around sampled launches in the
-timed region), and the binary64 oracle timed on a bounded sample on the host.
+timed region), the error of the propagated state against the exact coherent
+state with its budget, and the binary64 oracle timed on a bounded sample on
+the host.
 """
 import argparse
 import json
@@ -27,7 +32,7 @@ if ROOT not in sys.path:
 
 METRIC = ("Gelem/s of H applied (procedural vs cached) & Chebyshev steps/s "
           "at stated err")
-PEAK_FP32_TFLOPS = 157.3   # MI355X vector fp32 (published)
+PEAK_FP32_TFLOPS = 157.3   # MI355X fp32: vector and dense matrix cores (published)
 PEAK_HBM_GBS = 8000.0
 
 
@@ -35,23 +40,28 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "dvr_toeplitz_D32768_pmc.txt")
-DVR_SOURCE = os.path.join(ROOT, "paper_2606_31598_amd", "csrc", "dvr.hip")
+CSRC = os.path.join(ROOT, "paper_2606_31598_amd", "csrc")
+# dominant kernel per --dvr-kernel: (counter summary, kernel source)
+PMC = {"mfma": (os.path.join(ROOT, "profiles", "dvr_toeplitz_mfma_D32768_pmc.txt"),
+                os.path.join(CSRC, "dvr_mfma.hip")),
+       "valu": (os.path.join(ROOT, "profiles", "dvr_toeplitz_D32768_pmc.txt"),
+                os.path.join(CSRC, "dvr.hip"))}
 
 
-def counted_traffic():
+def counted_traffic(kernel):
     """HBM bytes per launch of the dominant kernel from the committed
     FETCH_SIZE / WRITE_SIZE summary, or None when the kernel source has
     changed since the counters were taken."""
     import hashlib
-    if not os.path.exists(PMC_SUMMARY):
+    summary, source = PMC[kernel]
+    if not os.path.exists(summary):
         return None
     vals = {}
-    for line in open(PMC_SUMMARY):
+    for line in open(summary):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    digest = hashlib.sha256(open(DVR_SOURCE, "rb").read()).hexdigest()
+    digest = hashlib.sha256(open(source, "rb").read()).hexdigest()
     if vals.get("source_sha256") != digest:
         return None
     try:
@@ -139,8 +149,10 @@ def run_dvr(args):
     strat = {"procedural": pm.PROCEDURAL, "partial": pm.PARTIAL,
              "full": pm.FULL}[args.strategy]
     frac = {"procedural": 0.0, "partial": 0.5, "full": 1.0}[args.strategy]
-    log(f"DVR D={D} b={b} strategy={args.strategy}")
-    op = pm.Operator.dvr(D).plan(b, strat, frac)
+    prec = {"fp32": pm.FP32, "compensated": pm.FP32_COMPENSATED}[args.precision]
+    log(f"DVR D={D} b={b} strategy={args.strategy} precision={args.precision}")
+    kind = {"auto": 0, "valu": 1, "mfma": 2}[args.dvr_kernel]
+    op = pm.Operator.dvr(D).plan(b, strat, frac, precision=prec).set_dvr_kernel(kind)
     c, R = op.spectral_bounds()
     K = pm.cheb_order(R * dt, 1e-10)
     log(f"c={c:.6g} R={R:.6g} K={K} (H products per step)")
@@ -177,6 +189,7 @@ def run_dvr(args):
     red_avg = prof["reduce_ms"] / max(prof["reduce_n"], 1) / 1e3
     flops = 4.0 * D * D      # real entry x complex vector: 2 FMA per element
     achieved = flops / tile_avg / 1e12
+    mfma = args.dvr_kernel == "mfma" or (args.dvr_kernel == "auto" and D >= 16384)
     out = {
         "metric": METRIC, "value": value, "unit": "Gelem/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
@@ -185,19 +198,21 @@ def run_dvr(args):
         "data": "synthetic",
         "config": {"workload": f"sinc-DVR harmonic oscillator D={D}, x in [-20,20], "
                                f"wavepacket x0=3 sigma=1, Chebyshev dt={dt}, "
-                               f"K={K} products per step, {args.strategy} b={b}",
-                   "D": D, "nvec": 1, "K": K, "dt": dt, "block_size": b,
-                   "strategy": args.strategy},
+                               f"K={K} products per step, {args.strategy}, "
+                               f"{args.precision} arithmetic",
+                   "D": D, "nvec": 1, "K": K, "dt": dt, "strategy": args.strategy,
+                   "arithmetic": args.precision},
         "cheb_steps_per_s": args.steps / wall,
         "h_products_per_s": args.steps * K / wall,
         "tile_kernel_avg_us": tile_avg * 1e6,
         "reduce_kernel_avg_us": red_avg * 1e6,
         "timed_launches": {"tile": prof["tile_n"], "reduce": prof["reduce_n"],
                            "sampled_every": args.profile_every},
-        "roofline": {"bound": "alu", "achieved": achieved,
+        "dominant_kernel": "dvr_toeplitz_mfma_kernel" if mfma else "dvr_toeplitz_kernel",
+        "roofline": {"bound": "mfma" if mfma else "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": counted_traffic()},
+                     "traffic": counted_traffic("mfma" if mfma else "valu")},
     }
 
     if args.modes:
@@ -207,7 +222,7 @@ def run_dvr(args):
         for name, st, f in [("procedural", pm.PROCEDURAL, 0.0),
                             ("partial50", pm.PARTIAL, 0.5),
                             ("full", pm.FULL, 1.0)]:
-            o2 = pm.Operator.dvr(D).plan(b, st, f)
+            o2 = pm.Operator.dvr(D).plan(b, st, f, precision=prec).set_dvr_kernel(kind)
             t, pr = measure_apply(pm, o2, X, args.mode_reps)
             info = o2.plan_info()
             ta = pr["tile_ms"] / max(pr["tile_n"], 1) / 1e3
@@ -223,8 +238,13 @@ def run_dvr(args):
     if args.cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline_dvr(D)
+        n_steps = args.warmup + args.steps
         out["err_vs_exact"] = stated_error_dvr(psi_host, D, t_total)
+        out["err_steps"] = n_steps
         out["err_time"] = t_total
+        # target: 1e-4 after 200 steps, rounding errors of independent steps
+        # adding in quadrature
+        out["err_budget"] = 1e-4 * math.sqrt(n_steps / 200.0)
     return out
 
 
@@ -237,7 +257,9 @@ def pmc_probe(args):
     from paper_2606_31598_amd import procmv as pm
     from paper_2606_31598_amd import workloads
     D = args.D
-    op = pm.Operator.dvr(D).plan(args.block)
+    prec = {"fp32": pm.FP32, "compensated": pm.FP32_COMPENSATED}[args.precision]
+    kind = {"auto": 0, "valu": 1, "mfma": 2}[args.dvr_kernel]
+    op = pm.Operator.dvr(D).plan(args.block, precision=prec).set_dvr_kernel(kind)
     X = torch.from_numpy(workloads.gaussian_vectors(D, 1, seed=2).astype(np.complex64)).cuda()
     Y = torch.empty_like(X)
     for _ in range(20):
@@ -259,6 +281,10 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--strategy", default="procedural",
                     choices=["procedural", "partial", "full"])
+    ap.add_argument("--precision", default="compensated", choices=["fp32", "compensated"],
+                    help="binary32 arithmetic of the products and the recurrence")
+    ap.add_argument("--dvr-kernel", default="mfma", choices=["auto", "valu", "mfma"],
+                    help="procedural sinc-DVR product: matrix-core or VALU Toeplitz kernel")
     ap.add_argument("--profile-every", type=int, default=16)
     ap.add_argument("--mode-reps", type=int, default=50)
     ap.add_argument("--no-modes", dest="modes", action="store_false")

@@ -62,10 +62,24 @@ typedef enum {
     PROCMV_FULL = 2
 } procmv_strategy;
 
-/* Arithmetic of the block products. */
+/* Arithmetic of the block products.
+ * PROCMV_FP32_COMPENSATED (sinc-DVR operators only; paper Sec. VII centered
+ * Chebyshev propagation with the analytic blocks of Sec. III): the same
+ * binary32 entries and binary32 operations, arranged against the
+ * cancellation of the kinetic stencil (entries ~1/dx^2 with vanishing row
+ * sums acting on smooth states).  The tile kernels apply the operator
+ * without the band 0 < |i - j| < W (W = min(64, D)); the reduction adds the
+ * band in difference form, sum_band t(i-j) (x_j - x_i), and the rest of the
+ * row as the per-row constant C_i = d + sum_band t(i-j) + V_i (binary64 sum
+ * of the binary32 entries, applied as a hi + lo binary32 pair), which is the
+ * same operator.  Chebyshev recurrence vectors are carried as hi + lo
+ * binary32 pairs updated with exact products and two-sums; the coefficient
+ * sum and the norms stay binary64.  Products, propagation, the imaginary-
+ * time filter and the Lanczos bounds all use it; batches do not. */
 typedef enum {
-    PROCMV_FP32 = 0,       /* binary32 entries, binary32 accumulation        */
-    PROCMV_SPLIT_BF16 = 1  /* hi/lo bfloat16 split on MFMA, fp32 accumulation */
+    PROCMV_FP32 = 0,             /* binary32 entries, binary32 accumulation        */
+    PROCMV_SPLIT_BF16 = 1,       /* hi/lo bfloat16 split on MFMA, fp32 accumulation */
+    PROCMV_FP32_COMPENSATED = 2  /* binary32, difference-form band, hi + lo vectors */
 } procmv_precision;
 
 /* Sinc-DVR parameters (analytic generation, paper Sec. III).  Grid
@@ -172,8 +186,9 @@ procmv_status procmv_kron_apply(procmv_op_t HB, const procmv_op_t* B, int32_t n_
  * d_S, HS, A, g) and the centered Chebyshev expansion of
  * procmv_chebyshev_propagate (paper Sec. VII: the example propagates its
  * system-bath state this way).  Every term is one procmv_kron_apply plus one
- * vector kernel (q_{k+1} = 2 (H q_k - c q_k)/R - q_{k-1} in binary64, rounded
- * to complex64; binary64 coefficient sum).  spec_c, spec_R: the caller's
+ * binary32 vector kernel (q_{k+1} = 2 alpha (H q_k - c q_k) - q_{k-1},
+ * alpha = 1/R rounded down to a binary32 value and R widened to 1/alpha,
+ * alpha c as a hi + lo pair; binary64 coefficient sum).  spec_c, spec_R: the caller's
  * spectral centre and half-width (R > 0; they must enclose the spectrum, e.g.
  * from procmv_lanczos_bounds-style estimates with a margin).  K <= 0:
  * procmv_cheb_order(R dt, 1e-10).  psi: device complex64, d_S * d_B entries
@@ -295,6 +310,26 @@ procmv_status procmv_autotune(procmv_op_t H, int32_t nvec, int32_t reps,
  * modes and block sizes. */
 procmv_status procmv_set_tile_shape(procmv_op_t H, int32_t shape);
 
+/* Kernel of the procedural sinc-DVR product (paper Sec. III analytic
+ * generation fused with the block product; the operator is Toeplitz plus a
+ * diagonal): kind 1 = VALU Toeplitz kernel (symbol window in LDS, binary32
+ * FMA), kind 2 = matrix-core Toeplitz kernel for one-vector launches (32 x 32
+ * Toeplitz blocks T_d shared by every output block, binary32 MFMA
+ * 32x32x2), kind 0 = automatic (matrix cores for one vector from
+ * D = 16384 on, VALU otherwise).  Launches of several vectors always take
+ * the VALU kernel.  Both apply the same binary32 entries; sums differ in
+ * order only. */
+procmv_status procmv_set_dvr_kernel(procmv_op_t H, int32_t kind);
+
+/* Tile shape the VALU tile kernel runs for a requested shape (0-2), a launch
+ * of nvec vectors (1, 2, 4 or 8) on an operator of dimension D: the largest
+ * shape not above `shape` whose tile rows 4 RW (RW = (8, 16, 32) / (2 nvec))
+ * fit the super-tile edge (64, 128 or 256, from D) and, when the super-tiles
+ * read a block cache of block size cache_block (0 = none), divide
+ * cache_block, so that a cached tile never leaves its b x b slot.  Host
+ * only; -1 for arguments out of range. */
+int32_t procmv_tile_shape_fit(int32_t nvec, int32_t shape, int64_t D, int32_t cache_block);
+
 /* Measured microbenchmark of one (operator, plan) pair (paper Sec. IV-C,
  * Eq. measured_matvec_time): creates the operator, plans it, times the cache
  * fill (the fill kernels re-run on the allocated slots: allocation is left
@@ -351,20 +386,48 @@ procmv_status procmv_plan_model_time(const procmv_machine_model* mm, int64_t D,
                                      double cache_fraction, int64_t reuse,
                                      double* t_fill_s, double* t_apply_s);
 
-/* Choose among the memory-feasible candidates the one with the smallest
- * score: planner 0 = analytic t_fill + reuse t_apply (Algorithm 1),
- * planner 1 = learned exp(f(z)) (Algorithm 3, ranking by the surrogate's
- * predicted total time).  mlp_params: procmv_mlp_param_count() floats;
- * mlp_norm: 16 floats (feature means then deviations).  All host pointers.
+/* Rank the memory-feasible candidates (paper Sec. IV-B, Algorithm 1's
+ * enumeration and memory test, Eq. planner_memory_constraint; block sizes
+ * above D are skipped except the smallest) by a model score, best first:
+ * planner 0 = analytic t_fill + reuse t_apply (Algorithm 1 with the
+ * procmv_plan_model_time model), planner 1 = learned exp(f(z)), the
+ * surrogate's predicted total time (Algorithm 3, Eq. nn_pred_time).
+ * mlp_params: procmv_mlp_param_count() floats; mlp_norm: 16 floats
+ * (feature means then deviations).  order_out / score_out (HOST, room for
+ * procmv_plan_candidate_count() entries, may be NULL) receive the candidate
+ * indices and scores; *n_out the number of feasible candidates.
  * PROCMV_ERR_INFEASIBLE_PLAN when no candidate fits. */
+procmv_status procmv_plan_rank(int32_t planner, const procmv_machine_model* mm,
+                               const float* mlp_params, const float* mlp_norm,
+                               int64_t D, int32_t nvec, double budget_bytes,
+                               int64_t reuse, int32_t family, int32_t* order_out,
+                               double* score_out, int32_t* n_out);
+
+/* The best-ranked candidate of procmv_plan_rank (planner 0 or 1) and its
+ * score.  Planners 2 and 3 time plans of an operator and are only offered by
+ * procmv_plan_auto (PROCMV_ERR_INVALID_ARG here). */
 procmv_status procmv_plan_choose(int32_t planner, const procmv_machine_model* mm,
                                  const float* mlp_params, const float* mlp_norm,
                                  int64_t D, int32_t nvec, double budget_bytes,
                                  int64_t reuse, int32_t family,
                                  int32_t* best_idx, double* best_score);
 
-/* procmv_plan_choose for this operator, then procmv_plan with the choice
- * (binary32). */
+/* Candidates timed by the measured planners of procmv_plan_auto. */
+#define PROCMV_PLAN_K_BENCH 4
+
+/* Choose a plan for this operator and apply it (procmv_plan, binary32):
+ *   planner 0: analytic (Algorithm 1), the best of procmv_plan_rank(0);
+ *   planner 1: learned (Algorithm 3, direct), the best of procmv_plan_rank(1);
+ *   planner 2: measured (Algorithm 2): the PROCMV_PLAN_K_BENCH best analytic
+ *              candidates are each timed with procmv_measure on this
+ *              operator's generator, seed and parameters (1 warm-up, 3 timed
+ *              products), and the smallest measured t_fill + reuse t_apply
+ *              wins (Eq. bench_argmin; one task, W = 1);
+ *   planner 3: hybrid (Algorithm 3 with local measurement): the same over
+ *              the PROCMV_PLAN_K_BENCH best learned candidates.
+ * Planners 2 and 3 allocate and free the measured plans' memory and
+ * SYNCHRONISE the stream; a timed candidate that does not fit is skipped.
+ * *chosen_idx (may be NULL) receives the candidate index. */
 procmv_status procmv_plan_auto(procmv_op_t H, int32_t nvec, double budget_bytes,
                                int64_t reuse, int32_t planner,
                                const procmv_machine_model* mm,

@@ -232,6 +232,38 @@ class DVR:
         H[idx, idx] = v + d
         return H
 
+    def apply_fft(self, X, rounded=True) -> np.ndarray:
+        """Binary64 product H X of the same entries as ``apply_rows``, for
+        any D: the Toeplitz part sum_j t(i - j) x_j is a linear convolution,
+        evaluated by embedding the symbol t(-(D-1)) .. t(D-1) in a circulant
+        of length N >= 2D - 1 and multiplying in Fourier space (numpy FFT);
+        the diagonal (v_i + d) x_i is added directly.  X: (nvec, D)."""
+        D = self.D
+        tk = self.tk32.astype(np.float64) if rounded else self.tk64
+        v = self.v32.astype(np.float64) if rounded else self.v64
+        d = self.d32 if rounded else self.d0
+        X = np.atleast_2d(np.asarray(X, dtype=np.complex128))
+        N = 1 << int(np.ceil(np.log2(2 * D - 1))) if D > 1 else 1
+        sym = self._fft_symbol(N, tk)
+        Xp = np.zeros((X.shape[0], N), np.complex128)
+        Xp[:, :D] = X
+        Y = np.fft.ifft(np.fft.fft(Xp, axis=1) * sym[None, :], axis=1)[:, :D]
+        return Y + (v + d)[None, :] * X
+
+    def _fft_symbol(self, N, tk):
+        """FFT of the circulant column c[k] = t(k) for 0 <= k < D,
+        c[N - k] = t(-k) = t(k) for 0 < k < D, zero elsewhere (t(0) = 0)."""
+        key = (N, tk.ctypes.data if tk is self.tk64 else "r")
+        cache = getattr(self, "_sym_cache", None)
+        if cache is not None and cache[0] == key:
+            return cache[1]
+        c = np.zeros(N, np.float64)
+        c[1:self.D] = tk[1:self.D]
+        c[N - self.D + 1:] = tk[1:self.D][::-1]
+        sym = np.fft.fft(c)
+        self._sym_cache = (key, sym)
+        return sym
+
     def apply_rows(self, X, rows=None, rounded=True) -> np.ndarray:
         """Row-by-row binary64 product with the generated (or exact) entries."""
         D = self.D

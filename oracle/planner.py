@@ -141,3 +141,117 @@ def zscore_fit(x):
     sd = x.std(0)
     sd[sd == 0] = 1.0
     return mu, sd
+
+
+# ------------------------------------------- analytic planner (Algorithm 1)
+# The paper's cost score (Eq. planner_cost_score) leaves the effective
+# throughput R_eff and the penalties Pi_cache, Pi_mem undefined.  The reading
+# used here makes them a time model of one product built from the runtime
+# model of Sec. V: source and contraction overlap (Eq. runtime_overlap), a
+# generated entry costs 1/R_gen (Eqs. seed_source_time, analytic_source_time
+# with the metadata and latency terms folded into one launch cost), a cached
+# entry costs its bytes over the cache bandwidth; the cache penalty becomes
+# the fill time, the memory penalty the feasibility test
+# (Eq. planner_memory_constraint).  Score = t_fill + reuse t_apply.
+
+PLAN_BLOCKS = (128, 256, 512, 1024, 2048, 4096)
+PLAN_MODES = ((0, 0.0), (1, 0.25), (1, 0.5), (1, 0.75), (2, 1.0))   # (strategy, f)
+PROCEDURAL, PARTIAL, FULL = 0, 1, 2
+
+
+def candidates():
+    """[(b, strategy, f)]: index = 5 log2(b / 128) + mode."""
+    return [(b, st, f) for b in PLAN_BLOCKS for st, f in PLAN_MODES]
+
+
+def super_edge(D):
+    """Work-unit edge 64 se: the largest se in {4, 2} giving >= 45 bands of
+    the dimension, else 1."""
+    for se in (4, 2):
+        if -(-D // (64 * se)) >= 45:
+            return 64 * se
+    return 64
+
+
+def uses_matrix_cores(family, strategy, nvec):
+    """Binary32 routing: matrix cores for 8+ vectors, or 4+ with every pair
+    cached; the procedural sinc-DVR operator always takes its Toeplitz
+    kernel."""
+    if family == 1 and strategy == PROCEDURAL:
+        return False
+    return nvec >= 8 or (nvec >= 4 and strategy == FULL)
+
+
+def vector_blocks(nvec, matrix_cores):
+    """Launch blocks of a product: 16 vectors on the matrix cores, else the
+    largest of 8, 4, 2, 1 not above what is left."""
+    out = []
+    r = nvec
+    while r > 0:
+        k = min(r, 16) if matrix_cores else next(c for c in (8, 4, 2, 1) if c <= r)
+        out.append(k)
+        r -= k
+    return out
+
+
+def plan_memory(D, nvec, family, b, strategy, f, reuse):
+    """(M_op, M_work) bytes: the cache is cached canonical pairs x b^2 x bytes
+    per entry (8 complex64, 4 for the real sinc-DVR entries); the workspace
+    holds one partial slot per band plus one (per block of 512 columns for
+    the procedural sinc-DVR kernel) for the largest vector block (16 on the
+    matrix cores), input and output, and with reuse the two Chebyshev
+    vectors (complex64 + complex128)."""
+    nb = -(-D // b)
+    npair = n_pair(nb)
+    p = npair if strategy == FULL else int(math.floor(f * npair)) if strategy == PARTIAL else 0
+    be = 8.0 if family == 0 else 4.0
+    m_op = p * b * b * be
+    mc = uses_matrix_cores(family, strategy, nvec)
+    blk = 16 if mc else max(vector_blocks(nvec, False)[0], 1)
+    if family == 1 and strategy == PROCEDURAL and not mc:
+        slots = -(-D // 512)
+    else:
+        slots = -(-D // super_edge(D)) + 1
+    m_work = slots * blk * D * 8.0 + 2.0 * nvec * D * 8.0
+    if reuse > 1:
+        m_work += nvec * D * (8.0 + 16.0)
+    return m_op, m_work
+
+
+def analytic_time(mm, D, nvec, family, b, strategy, f, reuse):
+    """(t_fill, t_apply) seconds of one plan under the machine constants
+    mm = {gen_rate: (GUE, DVR) canonical entries/s, dvr_rate: Toeplitz
+    elements/s, cache_bw: bytes/s, flop_rate: flop/s, launch_s: s}."""
+    m_op, _ = plan_memory(D, nvec, family, b, strategy, f, reuse)
+    be = 8.0 if family == 0 else 4.0
+    cached = m_op / be                          # cached canonical entries
+    canonical = 0.5 * D * (D + 1)               # each applied twice (Hermitian)
+    generated = max(0.0, canonical - cached)
+    mc = uses_matrix_cores(family, strategy, nvec)
+    launches = len(vector_blocks(nvec, mc))
+    if family == 1 and strategy == PROCEDURAL and not mc:
+        t_src = D * D * nvec / mm["dvr_rate"]   # analytic source, per vector
+    else:                                       # every launch regenerates / re-reads
+        t_src = launches * (generated / mm["gen_rate"][family] + m_op / mm["cache_bw"])
+    t_mv = 8.0 * D * D * nvec / mm["flop_rate"]  # Eq. generic_matvec_flops
+    t_apply = mm["launch_s"] + max(t_src, t_mv)  # Eq. runtime_overlap
+    t_fill = cached / mm["gen_rate"][family] + m_op / mm["cache_bw"]
+    return t_fill, t_apply
+
+
+def analytic_choice(mm, D, nvec, budget, reuse, family, alpha=0.9):
+    """Algorithm 1: the feasible candidate (block not above D except the
+    smallest, M_tot <= alpha budget) with the smallest t_fill + reuse t_apply;
+    returns (index, score), index None when nothing fits."""
+    best, best_score = None, math.inf
+    for q, (b, st, f) in enumerate(candidates()):
+        if b > D and b != PLAN_BLOCKS[0]:
+            continue
+        m_op, m_work = plan_memory(D, nvec, family, b, st, f, reuse)
+        if not feasible(m_op + m_work, budget, alpha):
+            continue
+        tf, ta = analytic_time(mm, D, nvec, family, b, st, f, reuse)
+        score = tf + reuse * ta
+        if score < best_score:
+            best, best_score = q, score
+    return best, best_score

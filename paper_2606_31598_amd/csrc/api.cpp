@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -61,11 +62,23 @@ struct procmv_op {
     float* d_text = nullptr;  // symmetric symbol t(k), k in (-D, D), zero at 0
     double d_const = 0.0;   // constant diagonal paired with the binary32 tables
     double dx = 0.0, vmax = 0.0;
+    std::vector<float> h_tk, h_v;   // host copies of the binary32 tables
+    // compensated arithmetic (precision PROCMV_FP32_COMPENSATED, sinc-DVR):
+    // the tile kernels read tables without the band |i - j| < near_w, the
+    // reduction adds the band in difference form and C_i x_i
+    int32_t near_w = 0;
+    float* d_text_far = nullptr;
+    float* d_tk_far = nullptr;
+    float* d_vzero = nullptr;
+    float2* d_cv = nullptr;   // C_i = d + sum_{0<|k|<W, 0<=i+k<D} tk[|k|] + v_i as (hi, lo)
+    float2* d_qlo = nullptr;  // lo parts of the two recurrence vectors
+    size_t qlo_bytes = 0;
     // plan
     bool planned = false;
     int32_t b = 0, n_blk = 0;
     int strategy = 0, precision = 0;
     int tile_shape = -1;      // VALU tile shape (see launch_tile_apply); -1 = per class
+    int dvr_kernel = 0;       // procedural sinc-DVR product: 0 auto, 1 VALU, 2 matrix cores
     double frac = 0.0;
     int64_t n_pair = 0, p_cache = 0;
     int32_t* d_pair_slot = nullptr;
@@ -104,7 +117,11 @@ struct procmv_op {
 
     size_t slot_elem() const { return gen == 0 ? sizeof(float2) : sizeof(float); }
 
-    SourceArgs source() const
+    bool comp() const { return gen == 1 && precision == PROCMV_FP32_COMPENSATED; }
+
+    // Block source of the products; `exact` = the operator's own entries
+    // (the compensated products read the tables without the band).
+    SourceArgs source(bool exact = false) const
     {
         SourceArgs s{};
         s.gen = gen;
@@ -112,8 +129,8 @@ struct procmv_op {
         s.gue.k1 = (uint32_t)(seed >> 32);
         s.gue.s_off = s_off;
         s.gue.s_diag = s_diag;
-        s.dvr.tk = d_tk;
-        s.dvr.v = d_v;
+        s.dvr.tk = (comp() && !exact) ? d_tk_far : d_tk;
+        s.dvr.v = (comp() && !exact) ? d_vzero : d_v;
         s.pair_slot = (planned && p_cache > 0) ? d_pair_slot : nullptr;
         s.slots = d_slots;
         s.b = b;
@@ -138,6 +155,11 @@ struct procmv_op {
         dfree(d_tk);
         dfree(d_v);
         dfree(d_text);
+        dfree(d_text_far);
+        dfree(d_tk_far);
+        dfree(d_vzero);
+        dfree(d_cv);
+        dfree(d_qlo);
         dfree(d_P);
         dfree(d_q);
         dfree(d_acc);
@@ -257,6 +279,8 @@ procmv_status upload_dvr(procmv_op* op)
     op->d_const = op->dvr.compensate ? d0 - 2.0 * err : d0;
     op->dx = dx;
     op->vmax = vmax;
+    op->h_tk = tk;
+    op->h_v = v;
     std::vector<float> text(2 * D - 1, 0.f);
     for (int64_t k = 1; k < D; ++k) text[D - 1 + k] = text[D - 1 - k] = tk[k];
     HIP_TRY(hipMalloc((void**)&op->d_text, (2 * D - 1) * sizeof(float)));
@@ -269,11 +293,68 @@ procmv_status upload_dvr(procmv_op* op)
     return PROCMV_OK;
 }
 
+// Tables of the compensated arithmetic: symbol windows without the band
+// 0 < |k| < W, a zero site potential for the tile kernels, and the per-row
+// constant C_i = d + sum_{0<|k|<W, 0<=i+k<D} tk[|k|] + v_i (binary64 sum of
+// the binary32 entries, stored as a hi + lo pair), so that
+// (H x)_i = far_i + sum_band tk (x_j - x_i) + C_i x_i exactly.
+procmv_status upload_comp(procmv_op* op)
+{
+    if (op->d_cv) return PROCMV_OK;
+    const int64_t D = op->D;
+    const int32_t W = (int32_t)std::min<int64_t>(kNearBand, D);
+    std::vector<float> text(2 * D - 1, 0.f), tkf(D, 0.f);
+    for (int64_t k = W; k < D; ++k) {
+        text[D - 1 + k] = text[D - 1 - k] = op->h_tk[k];
+        tkf[k] = op->h_tk[k];
+    }
+    std::vector<float2> cv(D);
+    for (int64_t i = 0; i < D; ++i) {
+        double c = op->d_const + (double)op->h_v[i];
+        for (int32_t k = 1; k < W; ++k) {
+            if (i - k >= 0) c += (double)op->h_tk[k];
+            if (i + k < D) c += (double)op->h_tk[k];
+        }
+        float hi, lo;
+        split_f32(c, hi, lo);
+        cv[i] = make_float2(hi, lo);
+    }
+    const std::vector<float> zero(D, 0.f);
+    HIP_TRY(hipMalloc((void**)&op->d_text_far, (2 * D - 1) * sizeof(float)));
+    HIP_TRY(hipMalloc((void**)&op->d_tk_far, D * sizeof(float)));
+    HIP_TRY(hipMalloc((void**)&op->d_vzero, D * sizeof(float)));
+    HIP_TRY(hipMalloc((void**)&op->d_cv, D * sizeof(float2)));
+    HIP_TRY(hipMemcpy(op->d_text_far, text.data(), (2 * D - 1) * sizeof(float),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(op->d_tk_far, tkf.data(), D * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(op->d_vzero, zero.data(), D * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(op->d_cv, cv.data(), D * sizeof(float2), hipMemcpyHostToDevice));
+    op->near_w = W;
+    return PROCMV_OK;
+}
+
+// The compensated reduction's operands (null cv = plain reduction).
+void comp_fields(const procmv_op* op, ReduceArgs& r)
+{
+    if (!op->comp()) return;
+    r.cv = op->d_cv;
+    r.tk = op->d_tk;
+    r.W = op->near_w;
+}
+
 // What the reduction of a tile product must add up.
 struct TileOut {
     int32_t n_slots = 0;
     int32_t nv_stride = 0;
     const float* vdiag = nullptr;
+    float2* P = nullptr;      // partial slots written by the tile kernels
+};
+
+// Caller-provided partial buffer (the allocation-free product); null = the
+// operator's own, grown on demand.
+struct Scratch {
+    float2* p = nullptr;
+    size_t bytes = 0;
 };
 
 // Whether a block of `remaining` vectors goes to the matrix cores: always in
@@ -311,31 +392,48 @@ int chunk_vectors(const procmv_op* op, int remaining)
 // vectors, the MFMA kernel for vector blocks on the matrix cores, the generic
 // two-sided VALU tile kernel otherwise.
 procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
-                        hipStream_t s, TileOut& out)
+                        hipStream_t s, TileOut& out, const Scratch& scr = Scratch{})
 {
     const size_t ldp = (size_t)op->D;
     const bool mfma = use_mfma(op, nv);
     const bool toeplitz = !mfma && op->gen == 1 && op->p_cache == 0;
+    // one vector of a large operator: the Toeplitz blocks on the matrix cores
+    const bool tmfma = toeplitz && nv == 1 &&
+                       (op->dvr_kernel == 2 || (op->dvr_kernel == 0 && op->D >= kDvrMfmaMinD));
     const int variant = toeplitz ? dvr_toeplitz_variant((int32_t)op->D, nv) : 0;
     const int chunk = toeplitz ? dvr_toeplitz_chunk_of(variant) : 1;
-    out.n_slots = toeplitz ? (int32_t)((op->D + chunk - 1) / chunk) : op->n_super + 1;
-    out.vdiag = toeplitz ? op->d_v : nullptr;
+    out.n_slots = tmfma ? dvr_mfma_chunks((int32_t)op->D)
+                : toeplitz ? (int32_t)((op->D + chunk - 1) / chunk) : op->n_super + 1;
+    out.vdiag = (toeplitz && !op->comp()) ? op->d_v : nullptr;
     out.nv_stride = nv;
     const size_t need = (size_t)out.n_slots * out.nv_stride * ldp * sizeof(float2);
-    procmv_status st = ensure(op->d_P, op->P_bytes, need);
-    if (st != PROCMV_OK) return st;
+    if (scr.p) {
+        if (need > scr.bytes)
+            return fail(PROCMV_ERR_INVALID_ARG,
+                        "partial slots need %zu bytes, above the %zu-byte static workspace",
+                        need, scr.bytes);
+        out.P = scr.p;
+    } else {
+        procmv_status st = ensure(op->d_P, op->P_bytes, need);
+        if (st != PROCMV_OK) return st;
+        out.P = op->d_P;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool timed = op->prof_pair(0, e0, e1);
+    // no timing events on the allocation-free path (it creates nothing)
+    const bool timed = !scr.p && op->prof_pair(0, e0, e1);
     if (timed && !toeplitz) HIP_TRY(hipEventRecord(e0, s));
     if (toeplitz) {
         DvrToeplitzArgs a{};
         a.D = (int32_t)op->D;
-        a.text = op->d_text;
+        a.text = op->comp() ? op->d_text_far : op->d_text;
         a.X = X;
         a.ldx = ldx;
-        a.P = op->d_P;
+        a.P = out.P;
         a.ldp = (int64_t)ldp;
-        HIP_TRY(launch_dvr_toeplitz(a, nv, variant, s, timed ? e0 : nullptr, e1));
+        if (tmfma)
+            HIP_TRY(launch_dvr_toeplitz_mfma(a, s, timed ? e0 : nullptr, e1));
+        else
+            HIP_TRY(launch_dvr_toeplitz(a, nv, variant, s, timed ? e0 : nullptr, e1));
     } else {
         TileArgs a{};
         a.src = op->source();
@@ -346,7 +444,7 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
         a.st_list = op->d_st;
         a.X = X;
         a.ldx = ldx;
-        a.P = op->d_P;
+        a.P = out.P;
         a.ldp = (int64_t)ldp;
         if (mfma) {
             HIP_TRY(launch_tile_mfma(a, op->precision == PROCMV_SPLIT_BF16 ? 1 : 0,
@@ -384,11 +482,14 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
 }
 
 procmv_status run_reduce(procmv_op* op, const ReduceArgs& r, Epi mode,
-                         hipStream_t s)
+                         hipStream_t s, bool untimed = false)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool timed = op->prof_pair(1, e0, e1);
-    HIP_TRY(launch_reduce(r, mode, s, timed ? e0 : nullptr, e1));
+    const bool timed = !untimed && op->prof_pair(1, e0, e1);
+    if (r.cv)
+        HIP_TRY(launch_reduce_comp(r, mode, s, timed ? e0 : nullptr, e1));
+    else
+        HIP_TRY(launch_reduce(r, mode, s, timed ? e0 : nullptr, e1));
     return PROCMV_OK;
 }
 
@@ -400,7 +501,7 @@ ReduceArgs reduce_args(procmv_op* op, int nv, const TileOut& t)
     r.n_slots = t.n_slots;
     r.nv_stride = t.nv_stride;
     r.vdiag = t.vdiag;
-    r.P = op->d_P;
+    r.P = t.P;
     r.ldp = op->D;
     r.alpha = 1.0f;
     return r;
@@ -411,10 +512,10 @@ ReduceArgs reduce_args(procmv_op* op, int nv, const TileOut& t)
 // (X, Y, acc, alpha, beta, coefficients); the partial-buffer fields are
 // filled here.
 procmv_status run_product(procmv_op* op, const float2* X, int64_t ldx, int nv, ReduceArgs r,
-                          Epi mode, hipStream_t s)
+                          Epi mode, hipStream_t s, const Scratch& scr = Scratch{})
 {
     TileOut to;
-    procmv_status st = run_tiles(op, X, ldx, nv, s, to);
+    procmv_status st = run_tiles(op, X, ldx, nv, s, to, scr);
     if (st != PROCMV_OK) return st;
     ReduceArgs base = reduce_args(op, nv, to);
     r.D = base.D;
@@ -426,7 +527,7 @@ procmv_status run_product(procmv_op* op, const float2* X, int64_t ldx, int nv, R
     r.vdiag = base.vdiag;
     r.X = X;
     r.ldx = ldx;
-    return run_reduce(op, r, mode, s);
+    return run_reduce(op, r, mode, s, scr.p != nullptr);
 }
 
 
@@ -487,10 +588,18 @@ procmv_status procmv_plan(procmv_op_t H, int32_t block_size,
         return fail(PROCMV_ERR_INVALID_ARG, "unknown strategy %d", (int)strategy);
     if (strategy == PROCMV_PARTIAL && !(cache_fraction >= 0.0 && cache_fraction <= 1.0))
         return fail(PROCMV_ERR_INVALID_ARG, "cache fraction %g outside [0, 1]", cache_fraction);
-    if (precision != PROCMV_FP32 && precision != PROCMV_SPLIT_BF16)
+    if (precision != PROCMV_FP32 && precision != PROCMV_SPLIT_BF16 &&
+        precision != PROCMV_FP32_COMPENSATED)
         return fail(PROCMV_ERR_INVALID_ARG, "unknown precision %d", (int)precision);
+    if (precision == PROCMV_FP32_COMPENSATED && H->gen != PROCMV_GEN_SINC_DVR)
+        return fail(PROCMV_ERR_INVALID_ARG,
+                    "compensated arithmetic is defined for the sinc-DVR operator");
     hipStream_t s = (hipStream_t)stream;
     H->release_plan();
+    if (precision == PROCMV_FP32_COMPENSATED) {
+        st = upload_comp(H);
+        if (st != PROCMV_OK) return st;
+    }
     const int64_t D = H->D;
     H->b = block_size;
     H->n_blk = (int32_t)((D + block_size - 1) / block_size);
@@ -592,8 +701,13 @@ procmv_status procmv_plan_info(procmv_op_t H, procmv_plan_info_t* info)
     return PROCMV_OK;
 }
 
-procmv_status procmv_apply(procmv_op_t H, const void* X, int64_t ldx, void* Y,
-                           int64_t ldy, int32_t nvec, void* stream)
+}  // extern "C"
+
+namespace {
+
+// Y = H X with the partials in the operator's buffer or in `scr`.
+procmv_status apply_impl(procmv_op_t H, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                         int32_t nvec, void* stream, const Scratch& scr)
 {
     procmv_status st = check_op(H);
     if (st != PROCMV_OK) return st;
@@ -621,12 +735,24 @@ procmv_status procmv_apply(procmv_op_t H, const void* X, int64_t ldx, void* Y,
         r.alpha = 1.0f;
         r.beta_hi = bhi;
         r.beta_lo = blo;
-        st = run_product(H, Xc, ldx, nv, r, Epi::kApply, s);
+        comp_fields(H, r);
+        st = run_product(H, Xc, ldx, nv, r, Epi::kApply, s, scr);
         if (st != PROCMV_OK) return st;
         v0 += nv;
     }
     return PROCMV_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+procmv_status procmv_apply(procmv_op_t H, const void* X, int64_t ldx, void* Y,
+                           int64_t ldy, int32_t nvec, void* stream)
+{
+    return apply_impl(H, X, ldx, Y, ldy, nvec, stream, Scratch{});
+}
+
 
 procmv_status procmv_spectral_bounds(procmv_op_t H, double* c, double* R)
 {
@@ -836,13 +962,16 @@ procmv_status procmv_kron_propagate(procmv_op_t HB, const procmv_op_t* B, int32_
         return fail(PROCMV_ERR_INVALID_ARG, "bad d_S/nsteps/dt/R");
     const int64_t n = (int64_t)dS * HB->D;
     if (n > INT32_MAX) return fail(PROCMV_ERR_INVALID_ARG, "d_S d_B too large");
-    if (K <= 0) K = procmv_cheb_order(spec_R * dt, 1e-10);
+    // 1/R exact in binary32: the half-width is widened to 1/alpha
+    const float alpha = f32_down(1.0 / spec_R);
+    const double Reff = 1.0 / (double)alpha;
+    if (K <= 0) K = procmv_cheb_order(Reff * dt, 1e-10);
     if (K < 1) return fail(PROCMV_ERR_INVALID_ARG, "Chebyshev order could not be set");
     st = ensure(HB->d_kq, HB->kq_bytes, (size_t)2 * n * sizeof(float2));
     if (st != PROCMV_OK) return st;
     st = ensure(HB->d_kacc, HB->kacc_bytes, (size_t)(n + 1) * sizeof(double2));
     if (st != PROCMV_OK) return st;
-    const std::vector<double> j = bessel_j(spec_R * dt, K);
+    const std::vector<double> j = bessel_j(Reff * dt, K);
     std::vector<double2> a(K + 1);
     for (int k = 0; k <= K; ++k) {
         const double m = (k == 0 ? 1.0 : 2.0) * j[k];
@@ -851,7 +980,8 @@ procmv_status procmv_kron_propagate(procmv_op_t HB, const procmv_op_t* B, int32_
              : q == 2 ? double2{-m, 0.0} : double2{0.0, m};
     }
     const double2 phase{std::cos(spec_c * dt), -std::sin(spec_c * dt)};
-    const double alpha = 1.0 / spec_R;
+    float bhi, blo;
+    split_f32(-(double)alpha * spec_c, bhi, blo);
     hipStream_t s = (hipStream_t)stream;
     float2* P0 = (float2*)psi;
     float2* qa = HB->d_kq;
@@ -862,14 +992,15 @@ procmv_status procmv_kron_propagate(procmv_op_t HB, const procmv_op_t* B, int32_
         HIP_TRY(launch_kron_cheb_init(n, P0, acc, a[0], s));
         st = procmv_kron_apply(HB, B, n_int, dS, HS, A, g, P0, Yb, stream);
         if (st != PROCMV_OK) return st;
-        HIP_TRY(launch_kron_cheb_term(n, Yb, P0, qa, acc, alpha, spec_c, a[1], 1, s));
+        HIP_TRY(launch_kron_cheb_term(n, Yb, P0, qa, acc, alpha, bhi, blo, a[1], 1, s));
         // q_0 lives in psi, q_1 in qa; each term overwrites the older one
         float2* prev = P0;
         float2* cur = qa;
         for (int k = 1; k < K; ++k) {
             st = procmv_kron_apply(HB, B, n_int, dS, HS, A, g, cur, Yb, stream);
             if (st != PROCMV_OK) return st;
-            HIP_TRY(launch_kron_cheb_term(n, Yb, cur, prev, acc, alpha, spec_c, a[k + 1], 0, s));
+            HIP_TRY(launch_kron_cheb_term(n, Yb, cur, prev, acc, alpha, bhi, blo, a[k + 1], 0,
+                                          s));
             std::swap(prev, cur);
         }
         HIP_TRY(launch_cheb_finish((int32_t)n, 1, acc, n, phase, P0, n, norm2, s));
@@ -900,7 +1031,8 @@ namespace {
 // after each step when norms_out is given (synchronises then).
 procmv_status cheb_run(procmv_op_t H, void* psi, int64_t ld, int32_t nvec, int32_t K,
                        int32_t nsteps, const std::vector<double2>& a, double2 phase,
-                       float alpha, float bhi, float blo, double* norms_out, void* stream)
+                       float alpha, float bhi, float blo, float ghi, float glo,
+                       double* norms_out, void* stream)
 {
     procmv_status st = PROCMV_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -914,6 +1046,14 @@ procmv_status cheb_run(procmv_op_t H, void* psi, int64_t ld, int32_t nvec, int32
         if (st != PROCMV_OK) return st;
         st = ensure(H->d_norm, H->norm_bytes, (size_t)nv * sizeof(double));
         if (st != PROCMV_OK) return st;
+        const bool comp = H->comp();
+        if (comp) {
+            st = ensure(H->d_qlo, H->qlo_bytes, (size_t)2 * nv * D * sizeof(float2));
+            if (st != PROCMV_OK) return st;
+        }
+        // lo parts (compensated arithmetic): lo_a goes with psi's slot, lo_b with d_q's
+        float2* lo_a = comp ? H->d_qlo : nullptr;
+        float2* lo_b = comp ? H->d_qlo + (size_t)nv * D : nullptr;
         for (int step = 0; step < nsteps; ++step) {
             // q0 lives in psi (ld), q1 in d_q (ld = D); the recurrence
             // overwrites the older of the two.
@@ -931,6 +1071,14 @@ procmv_status cheb_run(procmv_op_t H, void* psi, int64_t ld, int32_t nvec, int32
             r.beta_lo = blo;
             r.a0 = a[0];
             r.a1 = a[1];
+            if (comp) {
+                comp_fields(H, r);
+                r.Yq1lo = lo_b;
+                r.Xlo_zero = lo_a;
+                r.ldylo = (int64_t)D;
+                r.gamma_hi = ghi;
+                r.gamma_lo = glo;
+            }
             st = run_product(H, qa, lda, nv, r, Epi::kChebFirst, s);
             if (st != PROCMV_OK) return st;
             // cur = qb (q1), prev = qa (q0)
@@ -938,6 +1086,8 @@ procmv_status cheb_run(procmv_op_t H, void* psi, int64_t ld, int32_t nvec, int32
             int64_t ldc = ldb;
             float2* prev = qa;
             int64_t ldpv = lda;
+            float2* cur_lo = lo_b;
+            float2* prev_lo = lo_a;
             for (int k = 1; k < K; ++k) {
                 ReduceArgs rs{};
                 rs.Y = prev;   // q_{k-1} in, q_{k+1} out
@@ -948,10 +1098,20 @@ procmv_status cheb_run(procmv_op_t H, void* psi, int64_t ld, int32_t nvec, int32
                 rs.beta_hi = bhi;
                 rs.beta_lo = blo;
                 rs.a0 = a[k + 1];
+                if (comp) {
+                    comp_fields(H, rs);
+                    rs.Xlo = cur_lo;
+                    rs.ldxl = (int64_t)D;
+                    rs.Ylo = prev_lo;
+                    rs.ldylo = (int64_t)D;
+                    rs.gamma_hi = ghi;
+                    rs.gamma_lo = glo;
+                }
                 st = run_product(H, cur, ldc, nv, rs, Epi::kChebStep, s);
                 if (st != PROCMV_OK) return st;
                 std::swap(cur, prev);
                 std::swap(ldc, ldpv);
+                std::swap(cur_lo, prev_lo);
             }
             HIP_TRY(launch_cheb_finish((int32_t)D, nv, H->d_acc, (int64_t)D, phase, P0, ld,
                                        H->d_norm, s));
@@ -1005,9 +1165,11 @@ procmv_status procmv_chebyshev_propagate(procmv_op_t H, void* psi, int64_t ld,
     }
     const double2 phase{std::cos(c * dt), -std::sin(c * dt)};
     const double dconst = H->gen == 1 ? H->d_const : 0.0;
-    float bhi, blo;
+    float bhi, blo, ghi, glo;
     split_f32((double)alpha * (dconst - c), bhi, blo);
-    return cheb_run(H, psi, ld, nvec, K, nsteps, a, phase, alpha, bhi, blo, norms_out, stream);
+    split_f32((double)alpha * c, ghi, glo);
+    return cheb_run(H, psi, ld, nvec, K, nsteps, a, phase, alpha, bhi, blo, ghi, glo, norms_out,
+                    stream);
 }
 
 namespace {
@@ -1078,9 +1240,11 @@ procmv_status procmv_chebyshev_filter(procmv_op_t H, void* psi, int64_t ld, int3
         return fail(PROCMV_ERR_INVALID_ARG, "e^{-tau (c - R)} = %g is out of range", scale);
     const double2 phase{scale, 0.0};
     const double dconst = H->gen == 1 ? H->d_const : 0.0;
-    float bhi, blo;
+    float bhi, blo, ghi, glo;
     split_f32((double)alpha * (dconst - c), bhi, blo);
-    return cheb_run(H, psi, ld, nvec, K, 1, a, phase, alpha, bhi, blo, norms_out, stream);
+    split_f32((double)alpha * c, ghi, glo);
+    return cheb_run(H, psi, ld, nvec, K, 1, a, phase, alpha, bhi, blo, ghi, glo, norms_out,
+                    stream);
 }
 
 procmv_status procmv_get_entries(procmv_op_t H, int64_t r0, int64_t c0,
@@ -1093,7 +1257,7 @@ procmv_status procmv_get_entries(procmv_op_t H, int64_t r0, int64_t c0,
     if (nr < 0 || nc < 0 || r0 < 0 || c0 < 0 || r0 + nr > H->D || c0 + nc > H->D)
         return fail(PROCMV_ERR_INVALID_ARG, "window outside the matrix");
     if ((int64_t)nr * nc == 0) return PROCMV_OK;
-    SourceArgs src = H->source();
+    SourceArgs src = H->source(true);
     HIP_TRY(launch_get_entries(src, r0, c0, nr, nc, (float2*)out_dev, (hipStream_t)stream));
     return PROCMV_OK;
 }
@@ -1172,6 +1336,7 @@ struct procmv_batch {
     int64_t n_items = 0;
     BatchReduceItem* d_ritems = nullptr;       // apply epilogue
     BatchReduceItem* d_citems = nullptr;       // Chebyshev epilogue
+    std::vector<BatchReduceItem> h_citems;      // its host copy (outlives the async upload)
     int64_t* d_off = nullptr;
     float2* d_P = nullptr;
     float2* d_q = nullptr;
@@ -1256,11 +1421,14 @@ procmv_status batch_tiles(procmv_batch* B, const float2* xbase, hipStream_t s)
     L.grid = (int)std::min<int64_t>(B->grid, B->n_items);
     L.cached = 0;
     L.min_se = kSuper / 64;
+    L.cache_b = 0;
     bool any_cached = false, all_full = true;
     for (procmv_op* op : B->ops) {
         L.cached |= (op->p_cache > 0) ? 1 : 0;
         any_cached = any_cached || op->p_cache > 0;
         all_full = all_full && op->p_cache == op->n_pair;
+        // tiles of every cached instance must fit its slots: a common divisor
+        if (op->p_cache > 0) L.cache_b = std::gcd(L.cache_b, (int)op->b);
     }
     // the single-operator routing rule, for the batch as a whole
     L.mfma = mfma_path(B->gen, !any_cached, all_full, PROCMV_FP32, B->nv) ? 1 : 0;
@@ -1423,10 +1591,20 @@ procmv_status procmv_batch_configure(procmv_batch_t B, int32_t shape, int32_t gr
     return PROCMV_OK;
 }
 
+// Packed X and Y of a batch must be disjoint.
+bool batch_overlap(const procmv_batch* B, const void* X, const void* Y)
+{
+    const char* x = (const char*)X;
+    const char* y = (const char*)Y;
+    const size_t n = (size_t)B->total * sizeof(float2);
+    return x < y + n && y < x + n;
+}
+
 procmv_status procmv_batch_apply(procmv_batch_t B, const void* X, void* Y, void* stream)
 {
     if (!B) return fail(PROCMV_ERR_INVALID_ARG, "null batch");
-    if (!X || !Y || X == Y) return fail(PROCMV_ERR_INVALID_ARG, "bad vector pointers");
+    if (!X || !Y) return fail(PROCMV_ERR_INVALID_ARG, "bad vector pointers");
+    if (batch_overlap(B, X, Y)) return fail(PROCMV_ERR_INVALID_ARG, "X and Y overlap");
     return batch_enqueue_apply(B, (const float2*)X, (float2*)Y, (hipStream_t)stream);
 }
 
@@ -1434,7 +1612,8 @@ procmv_status procmv_batch_autotune(procmv_batch_t B, const void* X, void* Y, in
                                     void* stream, double* best_ms)
 {
     if (!B) return fail(PROCMV_ERR_INVALID_ARG, "null batch");
-    if (!X || !Y || X == Y || reps < 1) return fail(PROCMV_ERR_INVALID_ARG, "bad arguments");
+    if (!X || !Y || reps < 1) return fail(PROCMV_ERR_INVALID_ARG, "bad arguments");
+    if (batch_overlap(B, X, Y)) return fail(PROCMV_ERR_INVALID_ARG, "X and Y overlap");
     hipStream_t s = (hipStream_t)stream;
     int dev = 0, cus = 256;
     HIP_TRY(hipGetDevice(&dev));
@@ -1508,7 +1687,8 @@ procmv_status procmv_batch_propagate(procmv_batch_t B, void* psi, double dt, int
                       B->g_key[1] == spec_c && B->g_key[2] == spec_R;
     if (!same) {
         B->drop_graph();
-        std::vector<BatchReduceItem> ci(B->n);
+        std::vector<BatchReduceItem>& ci = B->h_citems;
+        ci.assign(B->n, BatchReduceItem{});
         for (int k = 0; k < B->n; ++k) {
             procmv_op* op = B->ops[k];
             ci[k] = BatchReduceItem{};
@@ -1522,8 +1702,9 @@ procmv_status procmv_batch_propagate(procmv_batch_t B, void* psi, double dt, int
             split_f32((double)alpha * (dconst - spec_c), ci[k].beta_hi, ci[k].beta_lo);
             ci[k].phase = double2{std::cos(spec_c * dt), -std::sin(spec_c * dt)};
         }
-        HIP_TRY(hipMemcpy(B->d_citems, ci.data(), B->n * sizeof(BatchReduceItem),
-                          hipMemcpyHostToDevice));
+        // ordered on the caller's stream after any replay still reading it
+        HIP_TRY(hipMemcpyAsync(B->d_citems, ci.data(), B->n * sizeof(BatchReduceItem),
+                               hipMemcpyHostToDevice, (hipStream_t)stream));
     }
     // One Chebyshev step over every instance.
     auto enqueue_step = [&](hipStream_t q) -> procmv_status {
@@ -1589,6 +1770,23 @@ procmv_status procmv_batch_propagate(procmv_batch_t B, void* psi, double dt, int
         for (size_t q = 0; q < n2.size(); ++q) norms_out[q] = std::sqrt(n2[q]);
     }
     return PROCMV_OK;
+}
+
+procmv_status procmv_set_dvr_kernel(procmv_op_t H, int32_t kind)
+{
+    procmv_status st = check_op(H);
+    if (st != PROCMV_OK) return st;
+    if (kind < 0 || kind > 2) return fail(PROCMV_ERR_INVALID_ARG, "kernel kind %d", kind);
+    H->dvr_kernel = kind;
+    return PROCMV_OK;
+}
+
+int32_t procmv_tile_shape_fit(int32_t nvec, int32_t shape, int64_t D, int32_t cache_block)
+{
+    if ((nvec != 1 && nvec != 2 && nvec != 4 && nvec != 8) || shape < 0 || shape > 2 || D < 1 ||
+        cache_block < 0 || (cache_block > 0 && cache_block % 64 != 0))
+        return -1;
+    return fit_tile_shape(nvec, shape, super_edge_tiles(D), cache_block);
 }
 
 procmv_status procmv_set_tile_shape(procmv_op_t H, int32_t shape)
@@ -1951,11 +2149,14 @@ procmv_status procmv_plan_model_time(const procmv_machine_model* mm, int64_t D, 
     return PROCMV_OK;
 }
 
-procmv_status procmv_plan_choose(int32_t planner, const procmv_machine_model* mm,
-                                 const float* mlp_params, const float* mlp_norm, int64_t D,
-                                 int32_t nvec, double budget_bytes, int64_t reuse,
-                                 int32_t family, int32_t* best_idx, double* best_score)
+procmv_status procmv_plan_rank(int32_t planner, const procmv_machine_model* mm,
+                               const float* mlp_params, const float* mlp_norm, int64_t D,
+                               int32_t nvec, double budget_bytes, int64_t reuse,
+                               int32_t family, int32_t* order_out, double* score_out,
+                               int32_t* n_out)
 {
+    if (D < 1 || nvec < 1 || reuse < 1 || !(budget_bytes > 0.0) || (family != 0 && family != 1))
+        return fail(PROCMV_ERR_INVALID_ARG, "bad planning problem");
     const int nc = procmv_plan_candidate_count();
     std::vector<float> feats;
     std::vector<int> ids;
@@ -1996,13 +2197,38 @@ procmv_status procmv_plan_choose(int32_t planner, const procmv_machine_model* mm
         if (e != PROCMV_OK) return e;
         for (size_t k = 0; k < ids.size(); ++k) score[k] = std::exp((double)y[k]);
     } else {
-        return fail(PROCMV_ERR_INVALID_ARG, "planner must be 0 (analytic) or 1 (learned)");
+        return fail(PROCMV_ERR_INVALID_ARG, "ranking planner must be 0 (analytic) or 1 (learned)");
     }
-    size_t best = 0;
-    for (size_t k = 1; k < ids.size(); ++k)
-        if (score[k] < score[best]) best = k;
-    if (best_idx) *best_idx = ids[best];
-    if (best_score) *best_score = score[best];
+    // ascending score; equal scores keep candidate order
+    std::vector<size_t> ord(ids.size());
+    for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](size_t a, size_t b) { return score[a] < score[b]; });
+    for (size_t k = 0; k < ord.size(); ++k) {
+        if (order_out) order_out[k] = ids[ord[k]];
+        if (score_out) score_out[k] = score[ord[k]];
+    }
+    if (n_out) *n_out = (int32_t)ord.size();
+    return PROCMV_OK;
+}
+
+procmv_status procmv_plan_choose(int32_t planner, const procmv_machine_model* mm,
+                                 const float* mlp_params, const float* mlp_norm, int64_t D,
+                                 int32_t nvec, double budget_bytes, int64_t reuse,
+                                 int32_t family, int32_t* best_idx, double* best_score)
+{
+    if (planner == 2 || planner == 3)
+        return fail(PROCMV_ERR_INVALID_ARG,
+                    "measured selection (planner %d) times plans of an operator: "
+                    "use procmv_plan_auto", planner);
+    int32_t order[64];
+    double score[64];
+    int32_t n = 0;
+    procmv_status st = procmv_plan_rank(planner, mm, mlp_params, mlp_norm, D, nvec, budget_bytes,
+                                        reuse, family, order, score, &n);
+    if (st != PROCMV_OK) return st;
+    if (best_idx) *best_idx = order[0];
+    if (best_score) *best_score = score[0];
     return PROCMV_OK;
 }
 
@@ -2013,10 +2239,41 @@ procmv_status procmv_plan_auto(procmv_op_t H, int32_t nvec, double budget_bytes,
 {
     procmv_status st = check_op(H);
     if (st != PROCMV_OK) return st;
-    int32_t idx = 0;
-    st = procmv_plan_choose(planner, mm, mlp_params, mlp_norm, H->D, nvec, budget_bytes, reuse,
-                            H->gen, &idx, nullptr);
+    if (planner < 0 || planner > 3)
+        return fail(PROCMV_ERR_INVALID_ARG, "planner must be 0, 1, 2 or 3");
+    // Algorithms 1 / 3 (direct): the best-ranked candidate.  Algorithm 2
+    // (planner 2) and the hybrid of Algorithm 3 (planner 3): the analytic or
+    // learned ranking keeps its K_bench best, each is timed on this
+    // operator's generator, and the smallest measured t_fill + reuse t_apply
+    // wins (Eq. bench_argmin with one task: W = 1).
+    int32_t order[64];
+    double score[64];
+    int32_t n = 0;
+    st = procmv_plan_rank(planner == 2 ? 0 : planner == 3 ? 1 : planner, mm, mlp_params,
+                          mlp_norm, H->D, nvec, budget_bytes, reuse, H->gen, order, score, &n);
     if (st != PROCMV_OK) return st;
+    int32_t idx = order[0];
+    if (planner >= 2) {
+        const int kb = std::min<int32_t>(n, PROCMV_PLAN_K_BENCH);
+        double best = INFINITY;
+        const void* gp = H->gen == PROCMV_GEN_SINC_DVR ? (const void*)&H->dvr : nullptr;
+        for (int k = 0; k < kb; ++k) {
+            int32_t b, s;
+            double f, tf = 0.0, ta = 0.0;
+            plan_candidate(order[k], b, s, f);
+            st = procmv_measure((procmv_generator)H->gen, H->seed, H->D, gp, nvec, b,
+                                (procmv_strategy)s, f, PROCMV_FP32, 1, 3, stream, &tf, &ta);
+            if (st == PROCMV_ERR_OOM) continue;          // does not fit after all
+            if (st != PROCMV_OK) return st;
+            const double t = tf + (double)reuse * ta;
+            if (t < best) {
+                best = t;
+                idx = order[k];
+            }
+        }
+        if (!(best < INFINITY))
+            return fail(PROCMV_ERR_INFEASIBLE_PLAN, "no ranked plan could be measured");
+    }
     int32_t b, s;
     double f;
     plan_candidate(idx, b, s, f);

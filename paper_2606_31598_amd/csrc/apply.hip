@@ -656,17 +656,10 @@ hipError_t launch_nv_batched(const BatchTileLaunch& b, hipStream_t s)
 
 }  // namespace
 
-// Largest tile shape <= shape whose tile rows (4 RW) fit the super-tile edge.
-static int fit_shape(int nv, int shape, int se)
-{
-    while (shape > 0 && 4 * (16 << shape) / (2 * nv) > 64 * se) --shape;
-    return shape;
-}
-
 // Tile shapes: rows per wave RW = (8, 16, 32) / (2 NV) for shape 0, 1, 2.
 hipError_t launch_tile_apply(const TileArgs& a, int nv, int shape, int n_st, hipStream_t s)
 {
-    shape = fit_shape(nv, shape, a.se);
+    shape = fit_tile_shape(nv, shape, a.se, a.src.pair_slot ? a.src.b : 0);
 #define PROCMV_SHAPES(NV, R0, R1, R2)                                  \
     if (shape == 0) return launch_nv<NV, R0>(a, n_st, s);              \
     if (shape == 1) return launch_nv<NV, R1>(a, n_st, s);              \
@@ -685,7 +678,7 @@ hipError_t launch_tile_apply(const TileArgs& a, int nv, int shape, int n_st, hip
 hipError_t launch_tile_apply_batched(const BatchTileLaunch& b0, hipStream_t s)
 {
     BatchTileLaunch b = b0;
-    b.shape = fit_shape(b.nv, b.shape, b.min_se);
+    b.shape = fit_tile_shape(b.nv, b.shape, b.min_se, b.cached ? b.cache_b : 0);
 #define PROCMV_SHAPES(NV, R0, R1, R2)                                  \
     if (b.shape == 0) return launch_nv_batched<NV, R0>(b, s);          \
     if (b.shape == 1) return launch_nv_batched<NV, R1>(b, s);          \

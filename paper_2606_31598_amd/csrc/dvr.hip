@@ -13,8 +13,6 @@
 // site potential v_i x_i and the constant diagonal.
 #include <hip/hip_ext.h>
 
-#include <cstdlib>
-
 #include "kernels.h"
 
 namespace procmv {
@@ -178,7 +176,6 @@ hipError_t launch_dvr_nv(const DvrToeplitzArgs& a, int variant, hipStream_t s, h
 
 int dvr_toeplitz_variant(int32_t D, int nv)
 {
-    if (const char* e = getenv("PROCMV_DVR_VARIANT")) return atoi(e);
     // measured on MI355X: x staged in LDS, 4 rows per lane, 16 columns per
     // step; at large D 1024-column chunks for one vector (half the partial
     // slots of 512) and 512 for more; 256-column chunks below

@@ -25,6 +25,22 @@ inline int super_edge_tiles(int64_t D)
     return 1;
 }
 
+// VALU tile shape actually launched: the largest shape <= `shape` whose tile
+// rows TR = 4 RW (RW = (8, 16, 32) / (2 nv) for shapes 0, 1, 2) fit the
+// super-tile edge 64 se and, when tiles are read from a block cache of block
+// size `cache_b` (0 = no cache), divide it, so that every cached tile lies
+// inside one b x b slot.
+inline int fit_tile_shape(int nv, int shape, int se, int cache_b)
+{
+    if (nv < 1) return 0;
+    while (shape > 0) {
+        const int tr = 4 * (16 << shape) / (2 * nv);
+        if (tr <= 64 * se && (cache_b == 0 || cache_b % tr == 0)) break;
+        --shape;
+    }
+    return shape;
+}
+
 // Where the entries of one tile come from.
 struct SourceArgs {
     int gen;                   // 0 Philox-GUE, 1 sinc-DVR
@@ -60,6 +76,7 @@ struct BatchTileLaunch {
     int gen, nv, shape, grid;
     int cached;               // some instance has cached block pairs
     int min_se;               // smallest super-tile edge (64-column tiles) of the instances
+    int cache_b;              // common divisor of the cached instances' block sizes (0 = none)
     int mfma;                 // matrix-core kernel (binary32) instead of the VALU one
 };
 
@@ -99,7 +116,22 @@ struct ReduceArgs {
     float alpha;              // 1/R (Chebyshev) or 1 (apply)
     float beta_hi, beta_lo;   // constant-diagonal term, hi + lo binary32 pair
     double2 a0, a1;           // Chebyshev coefficients of the epilogue
+    // compensated sinc-DVR epilogue (launch_reduce_comp); cv == null otherwise
+    const float2* cv;         // per-row constant C_i as (hi, lo)
+    const float* tk;          // binary32 kinetic symbol tk[k], k = 1..W-1
+    int32_t W;                // band width: the tile kernels skip |i - j| < W
+    const float2* Xlo;        // lo parts of X (ld ldxl); null = zero
+    int64_t ldxl;
+    float2* Ylo;              // kChebStep: lo of q_prev in, of q_next out (ld ldylo)
+    float2* Yq1lo;            // kChebFirst: lo of q1 out
+    float2* Xlo_zero;         // kChebFirst: lo buffer of q0, set to zero
+    int64_t ldylo;
+    float gamma_hi, gamma_lo; // alpha c as a hi + lo pair
 };
+
+// Band of the compensated sinc-DVR arithmetic: entries with |i - j| < W are
+// summed in difference form by the reduction, W = min(kNearBand, D).
+constexpr int kNearBand = 64;
 
 // Epilogue of the fixed-order reduction for output element (v, i) whose
 // summed partials are (sx, sy): add the site diagonal, scale, add the
@@ -179,6 +211,9 @@ hipError_t launch_tile_apply(const TileArgs& a, int nv, int shape, int n_st,
 hipError_t launch_tile_apply_batched(const BatchTileLaunch& b, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, Epi mode, hipStream_t s,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// Compensated reduction of the sinc-DVR operator (defined in comp.hip).
+hipError_t launch_reduce_comp(const ReduceArgs& a, Epi mode, hipStream_t s,
+                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // MFMA multi-vector tile product, nv <= 16 (defined in mfma.hip);
 // precision 0 = binary32 MFMA, 1 = split bfloat16.
 hipError_t launch_tile_mfma(const TileArgs& a, int precision, int n_st,
@@ -202,6 +237,12 @@ int dvr_toeplitz_chunk_of(int variant);
 hipError_t launch_dvr_toeplitz(const DvrToeplitzArgs& a, int nv, int variant,
                                hipStream_t s, hipEvent_t e0 = nullptr,
                                hipEvent_t e1 = nullptr);
+// Sinc-DVR Toeplitz product of one vector on the matrix cores (defined in
+// dvr_mfma.hip): partial slots = dvr_mfma_chunks(D), layout as above.
+constexpr int32_t kDvrMfmaMinD = 16384;   // default routing: from this D on
+int dvr_mfma_chunks(int32_t D);
+hipError_t launch_dvr_toeplitz_mfma(const DvrToeplitzArgs& a, hipStream_t s,
+                                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Batched reduction and completion (defined in batch.hip).
 hipError_t launch_reduce_batched(const BatchReduceArgs& a, Epi mode, hipStream_t s);
 hipError_t launch_finish_batched(const BatchReduceItem* items, int n, int nv,
@@ -238,12 +279,13 @@ struct KronMixArgs {
 };
 hipError_t launch_kron_mix(const KronMixArgs& a, hipStream_t s);
 // Chebyshev propagation of the system-bath operator (defined in kron.hip):
-// acc = coef q; and one term q_new = [2] alpha (Y - c q_k) [- q_prev] over
-// q_prev with acc += coef q_new (binary64).
+// acc = coef q; and one binary32 term q_new = [2] (alpha Y + beta q_k)
+// [- q_prev] over q_prev, beta = -alpha c as hi + lo, with acc += coef q_new
+// (binary64).
 hipError_t launch_kron_cheb_init(int64_t n, const float2* q, double2* acc, double2 coef,
                                  hipStream_t s);
 hipError_t launch_kron_cheb_term(int64_t n, const float2* Y, const float2* qk, float2* qprev,
-                                 double2* acc, double alpha, double c, double2 coef,
+                                 double2* acc, float alpha, float bhi, float blo, double2 coef,
                                  int first, hipStream_t s);
 // Lanczos vector steps (defined in lanczos.hip).  Partial buffers hold
 // lanczos_blocks(D) <= kLanczosMaxBlocks doubles each.

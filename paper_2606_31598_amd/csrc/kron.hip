@@ -67,26 +67,29 @@ namespace procmv {
 namespace {
 
 // One Chebyshev term of the system-bath propagation (paper Sec. VII,
-// Ht = (H - c)/R): with Y = H q_k,
-//   first:  q_new = alpha (Y - c q_k)
-//   later:  q_new = 2 alpha (Y - c q_k) - q_prev
-// written over q_prev, and acc += coef q_new in binary64.
+// Ht = (H - c)/R), in binary32 like the single-operator epilogue: with
+// Y = H q_k, h = alpha Y + (bhi + blo) q_k (alpha = 1/R exact in binary32,
+// bhi + blo = -alpha c as a hi + lo pair),
+//   first:  q_new = h
+//   later:  q_new = 2 h - q_prev
+// written over q_prev, and acc += coef q_new in binary64 (the coefficient
+// sum is the only binary64 arithmetic).
 __global__ __launch_bounds__(256) void kron_cheb_term_kernel(
     int64_t n, const float2* __restrict__ Y, const float2* __restrict__ qk,
-    float2* __restrict__ qprev, double2* __restrict__ acc, double alpha, double c,
+    float2* __restrict__ qprev, double2* __restrict__ acc, float alpha, float bhi, float blo,
     double2 coef, int first)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float2 y = Y[i], q = qk[i];
-    double rx = alpha * ((double)y.x - c * (double)q.x);
-    double ry = alpha * ((double)y.y - c * (double)q.y);
+    const float bx = __builtin_fmaf(bhi, q.x, blo * q.x);
+    const float by = __builtin_fmaf(bhi, q.y, blo * q.y);
+    float2 o = make_float2(__builtin_fmaf(alpha, y.x, bx), __builtin_fmaf(alpha, y.y, by));
     if (!first) {
         const float2 p = qprev[i];
-        rx = 2.0 * rx - (double)p.x;
-        ry = 2.0 * ry - (double)p.y;
+        o.x = __builtin_fmaf(2.0f, o.x, -p.x);
+        o.y = __builtin_fmaf(2.0f, o.y, -p.y);
     }
-    const float2 o = make_float2((float)rx, (float)ry);
     qprev[i] = o;
     double2 a = acc[i];
     a.x += coef.x * (double)o.x - coef.y * (double)o.y;
@@ -116,11 +119,11 @@ hipError_t launch_kron_cheb_init(int64_t n, const float2* q, double2* acc, doubl
 }
 
 hipError_t launch_kron_cheb_term(int64_t n, const float2* Y, const float2* qk, float2* qprev,
-                                 double2* acc, double alpha, double c, double2 coef,
+                                 double2* acc, float alpha, float bhi, float blo, double2 coef,
                                  int first, hipStream_t s)
 {
     hipLaunchKernelGGL(kron_cheb_term_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                       s, n, Y, qk, qprev, acc, alpha, c, coef, first);
+                       s, n, Y, qk, qprev, acc, alpha, bhi, blo, coef, first);
     return hipGetLastError();
 }
 

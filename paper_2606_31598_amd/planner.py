@@ -30,6 +30,12 @@ DEFAULT_MODEL = os.path.join(HERE, "data", "mi355x_planner_mlp.json")
 LOG2_D = range(12, 19)
 NVECS = (1, 2, 4, 8, 16, 32, 64)
 BUDGET_MAX = 256e9
+DEFAULT_HELDOUT = os.path.join(HERE, "data", "mi355x_plan_heldout.jsonl")
+# Problems the network never saw: dimensions 3 2^k and 5 2^k and vector
+# counts that are not powers of two (the training grid is D = 2^12..2^18,
+# nvec = 1, 2, 4, ..., 64).
+HELDOUT_D = (5120, 6144, 10240, 12288, 20480, 24576, 40960, 49152, 81920, 98304)
+HELDOUT_NVEC = (3, 5, 6, 12, 24, 48)
 
 
 def log(msg):
@@ -77,18 +83,20 @@ def load_planners(trials=DEFAULT_TRIALS, model=DEFAULT_MODEL):
     return mm, np.array(m["params"], np.float32), np.array(m["norm"], np.float32)
 
 
-def collect(out_path, log2_d=LOG2_D, nvecs=NVECS, families=(0, 1), reps=2):
+def collect(out_path, log2_d=LOG2_D, nvecs=NVECS, families=(0, 1), reps=2, dims=None,
+            calibrate_model=True):
     """Measure fill and product time of every memory-feasible candidate on the
     (D, nvec, family) grid; one JSON line per trial."""
     import torch
     torch.zeros(1, device="cuda")       # initialise the device before timing
     cands = pm.plan_candidates()
     n = 0
+    dims = list(dims) if dims is not None else [1 << k for k in log2_d]
     with open(out_path, "w") as fh:
-        mm = calibrate()
-        fh.write(json.dumps({"kind": "machine_model", **model_dict(mm)}) + "\n")
-        for k in log2_d:
-            D = 1 << k
+        if calibrate_model:
+            mm = calibrate()
+            fh.write(json.dumps({"kind": "machine_model", **model_dict(mm)}) + "\n")
+        for D in dims:
             for fam in families:
                 for nv in nvecs:
                     for q, (b, st, f) in enumerate(cands):
@@ -112,7 +120,7 @@ def collect(out_path, log2_d=LOG2_D, nvecs=NVECS, families=(0, 1), reps=2):
                         fh.write(json.dumps(rec) + "\n")
                         fh.flush()
                         n += 1
-                    log(f"D=2^{k} family={fam} nvec={nv}: {n} trials so far")
+                    log(f"D={D} family={fam} nvec={nv}: {n} trials so far")
     return n
 
 
@@ -212,9 +220,68 @@ def evaluate(table, mm, model, n=200, seed=777):
     return out
 
 
+def heldout_workloads(n=200, seed=4242):
+    """Held-out problems: (D, nvec) from the held-out sets, family, budget
+    log-uniform in [16, 256] GB and reuse log-uniform in [1, 500]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        out.append({"D": int(rng.choice(HELDOUT_D)), "nvec": int(rng.choice(HELDOUT_NVEC)),
+                    "family": int(rng.integers(0, 2)),
+                    "budget_gb": float(np.exp(rng.uniform(np.log(16.0), np.log(256.0)))),
+                    "reuse": max(1, int(round(np.exp(rng.uniform(0.0, np.log(500.0))))))})
+    return out
+
+
+def evaluate_heldout(table, mm, model, n=200, seed=4242, k_bench=4):
+    """Regret t_chosen / t_best - 1 against the exhaustive measured search on
+    problems outside the training grid, for the learned (Algorithm 3,
+    direct), analytic (Algorithm 1), measured (Algorithm 2: analytic top
+    k_bench, best measured) and hybrid (learned top k_bench, best measured)
+    planners and the fixed procedural plan b = 256.  The measured planners
+    take their times from the same exhaustive table."""
+    cands = pm.plan_candidates()
+    params = np.array(model["params"], np.float32)
+    norm = np.array(model["norm"], np.float32)
+    names = ("learned", "analytic", "measured", "hybrid", "procedural")
+    res = {k: [] for k in names}
+    qp = [q for q, c in enumerate(cands) if c[0] == 256 and c[1] == pm.PROCEDURAL][0]
+    used = 0
+    for w in heldout_workloads(n, seed):
+        D, nv, fam, bud, reuse = w["D"], w["nvec"], w["family"], w["budget_gb"] * 1e9, w["reuse"]
+        feas = {}
+        for q, (b, st, f) in enumerate(cands):
+            if b > D and b != cands[0][0]:
+                continue
+            _, _, fe = pm.plan_features(D, nv, bud, reuse, fam, b, st, f)
+            if fe and (D, nv, fam, q) in table:
+                tf, ta = table[(D, nv, fam, q)]
+                feas[q] = t_total(tf, ta, reuse)
+        if not feas:
+            continue
+        best = min(feas.values())
+        ol, _ = pm.plan_rank(1, D, nv, bud, reuse, fam, params=params, norm=norm)
+        oa, _ = pm.plan_rank(0, D, nv, bud, reuse, fam, mm=mm)
+        meas = lambda order: min(order[:k_bench], key=lambda q: feas.get(q, float("inf")))
+        for name, q in (("learned", ol[0]), ("analytic", oa[0]), ("measured", meas(oa)),
+                        ("hybrid", meas(ol)), ("procedural", qp)):
+            t = feas.get(q)
+            res[name].append(float("inf") if t is None else t / best - 1.0)
+        used += 1
+    out = {"n_workloads": used, "k_bench": k_bench}
+    for name, r in res.items():
+        r = np.array(r)
+        out[name] = {"mean_regret": float(np.mean(np.minimum(r, 1e3))),
+                     "median_regret": float(np.median(r)),
+                     "within_10pct": float(np.mean(r <= 0.10))}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["collect", "train", "evaluate", "all"])
+    ap.add_argument("cmd", choices=["collect", "train", "evaluate", "all", "collect-heldout",
+                                    "evaluate-heldout"])
+    ap.add_argument("--heldout", default=DEFAULT_HELDOUT)
     ap.add_argument("--trials", default=DEFAULT_TRIALS)
     ap.add_argument("--out", default=None)
     ap.add_argument("--model", default=DEFAULT_MODEL)
@@ -224,6 +291,18 @@ def main(argv=None):
     ap.add_argument("--max-log2d", type=int, default=18)
     ap.add_argument("--nvecs", default=",".join(str(v) for v in NVECS))
     args = ap.parse_args(argv)
+    if args.cmd == "collect-heldout":
+        fams = tuple(int(f) for f in args.families.split(","))
+        n = collect(args.out or args.heldout, nvecs=HELDOUT_NVEC, families=fams,
+                    reps=args.reps, dims=HELDOUT_D, calibrate_model=False)
+        log(f"{n} held-out trials written")
+        return
+    if args.cmd == "evaluate-heldout":
+        mm, _ = load_trials(args.trials)
+        _, table = load_trials(args.heldout)
+        model = json.load(open(args.model))
+        print(json.dumps(evaluate_heldout(table, mm, model)), flush=True)
+        return
     if args.cmd in ("collect", "all"):
         out = args.out or args.trials
         fams = tuple(int(f) for f in args.families.split(","))

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libprocmv.so")
 GEN_PHILOX_GUE = 0
 GEN_SINC_DVR = 1
 PROCEDURAL, PARTIAL, FULL = 0, 1, 2
-FP32, SPLIT_BF16 = 0, 1
+FP32, SPLIT_BF16, FP32_COMPENSATED = 0, 1, 2
 
 _STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "INFEASIBLE_PLAN",
            4: "NOT_PLANNED", 5: "HIP", 6: "INTERNAL"}
@@ -34,6 +34,8 @@ EXPORTS = [
     "procmv_plan_features", "procmv_plan_model_time", "procmv_plan_choose",
     "procmv_plan_auto", "procmv_mlp_param_count", "procmv_mlp_grad",
     "procmv_mlp_train", "procmv_mlp_predict", "procmv_set_tile_shape",
+    "procmv_tile_shape_fit", "procmv_plan_rank",
+    "procmv_set_dvr_kernel",
 ]
 
 
@@ -145,9 +147,15 @@ def load():
     L.procmv_plan_choose.argtypes = [c.c_int32, c.POINTER(MachineModel), f32p, f32p,
                                      c.c_int64, c.c_int32, c.c_double, c.c_int64,
                                      c.c_int32, i32p, f64p]
+    L.procmv_plan_rank.argtypes = [c.c_int32, c.POINTER(MachineModel), f32p, f32p,
+                                   c.c_int64, c.c_int32, c.c_double, c.c_int64,
+                                   c.c_int32, i32p, f64p, i32p]
     L.procmv_plan_auto.argtypes = [vp, c.c_int32, c.c_double, c.c_int64, c.c_int32,
                                    c.POINTER(MachineModel), f32p, f32p, vp, i32p]
     L.procmv_set_tile_shape.argtypes = [vp, c.c_int32]
+    L.procmv_set_dvr_kernel.argtypes = [vp, c.c_int32]
+    L.procmv_tile_shape_fit.argtypes = [c.c_int32, c.c_int32, c.c_int64, c.c_int32]
+    L.procmv_tile_shape_fit.restype = c.c_int32
     L.procmv_mlp_param_count.restype = c.c_int32
     L.procmv_mlp_grad.argtypes = [f32p, f32p, f32p, c.c_int32, f32p, f32p]
     L.procmv_mlp_train.argtypes = [f32p, f32p, c.c_int32, c.c_int32, c.c_float, f32p, f32p]
@@ -160,7 +168,7 @@ def load():
     for name in EXPORTS:
         if name in ("procmv_cheb_order", "procmv_destroy", "procmv_last_error",
                     "procmv_batch_destroy", "procmv_plan_candidate_count",
-                    "procmv_mlp_param_count"):
+                    "procmv_mlp_param_count", "procmv_tile_shape_fit"):
             continue
         getattr(L, name).restype = c.c_int
     _lib = L
@@ -236,6 +244,11 @@ def kron_propagate(HB, Bs, HS, As, g, psi, dt, nsteps, c, R, K=0, norms=False,
     return out
 
 
+def tile_shape_fit(nvec, shape, D, cache_block=0) -> int:
+    """VALU tile shape launched for a requested shape (see the header)."""
+    return int(load().procmv_tile_shape_fit(int(nvec), int(shape), int(D), int(cache_block)))
+
+
 def filter_order(z: float, tol: float = 1e-10) -> int:
     return int(load().procmv_filter_order(float(z), float(tol)))
 
@@ -294,6 +307,25 @@ def plan_choose(planner, D, nvec, budget_bytes, reuse, family, mm=None, params=N
                                      pp, nn, int(D), int(nvec), float(budget_bytes), int(reuse),
                                      int(family), ctypes.byref(idx), ctypes.byref(sc)))
     return idx.value, sc.value
+
+
+def plan_rank(planner, D, nvec, budget_bytes, reuse, family, mm=None, params=None,
+              norm=None):
+    """Feasible candidates best first: ([index], [score]) (planner 0
+    analytic, 1 learned)."""
+    nc = load().procmv_plan_candidate_count()
+    order = np.zeros(nc, np.int32)
+    score = np.zeros(nc, np.float64)
+    n = ctypes.c_int32()
+    pa = _f32(params) if params is not None else (None, None)
+    na = _f32(norm) if norm is not None else (None, None)
+    _check(load().procmv_plan_rank(int(planner), ctypes.byref(mm) if mm is not None else None,
+                                   pa[1], na[1], int(D), int(nvec), float(budget_bytes),
+                                   int(reuse), int(family),
+                                   order.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   score.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   ctypes.byref(n)))
+    return order[:n.value].tolist(), score[:n.value].tolist()
 
 
 def mlp_param_count():
@@ -394,7 +426,8 @@ class Operator:
 
     def plan_auto(self, nvec, budget_bytes, reuse, planner=1, mm=None, params=None,
                   norm=None, stream=None):
-        """Choose the plan with the analytic (0) or learned (1) planner and
+        """Choose the plan with the analytic (0), learned (1), measured (2:
+        analytic top-K timed) or hybrid (3: learned top-K timed) planner and
         apply it (binary32); returns the chosen candidate index."""
         idx = ctypes.c_int32()
         pa = _f32(params) if params is not None else (None, None)   # keep the arrays alive
@@ -493,6 +526,12 @@ class Operator:
         _check(load().procmv_autotune(self._h, int(nvec), int(reps), _stream(stream),
                                       ctypes.byref(sh), ctypes.byref(ms)))
         return sh.value, ms.value
+
+    def set_dvr_kernel(self, kind):
+        """Procedural sinc-DVR product kernel: 0 automatic, 1 VALU Toeplitz
+        kernel, 2 matrix-core Toeplitz kernel (one vector per launch)."""
+        _check(load().procmv_set_dvr_kernel(self._h, int(kind)))
+        return self
 
     def set_tile_shape(self, shape):
         _check(load().procmv_set_tile_shape(self._h, int(shape)))

@@ -51,6 +51,9 @@ def test_invalid_arguments_rejected_on_host():
     assert L.procmv_plan(h, 100, 0, 0.0, 0, None) == 1         # not a multiple of 64
     assert L.procmv_plan(h, 64, 9, 0.0, 0, None) == 1          # unknown strategy
     assert L.procmv_plan(h, 64, 1, 1.5, 0, None) == 1          # fraction outside [0, 1]
+    assert L.procmv_plan(h, 64, 0, 0.0, 2, None) == 1          # compensated: sinc-DVR only
+    assert b"sinc-DVR" in L.procmv_last_error()
+    assert L.procmv_plan(h, 64, 0, 0.0, 3, None) == 1          # unknown precision
     x = ctypes.c_void_p(16)
     assert L.procmv_apply(h, x, 100, x, 100, 1, None) == 4     # not planned
     info = procmv.PlanInfo()
@@ -107,3 +110,32 @@ def test_filter_order_matches_oracle():
         for tol in (1e-7, 1e-10, 1e-13):
             assert procmv.filter_order(z, tol) == ch.filter_order(z, tol)
     assert procmv.filter_order(-1.0, 1e-10) == -1
+
+
+def test_tile_shape_fit_keeps_cached_tiles_in_their_slot():
+    """Tile rows 4 RW must fit the super-tile edge and divide a cached block
+    size: one vector at shape 2 has 128-row tiles, allowed at D = 12000
+    (256-row super-tiles) only for block sizes that 128 divides."""
+    from paper_2606_31598_amd import procmv as pm
+    assert pm.tile_shape_fit(1, 2, 12000, 0) == 2
+    assert pm.tile_shape_fit(1, 2, 12000, 256) == 2
+    assert pm.tile_shape_fit(1, 2, 12000, 192) == 1
+    assert pm.tile_shape_fit(1, 2, 12000, 64) == 1
+    assert pm.tile_shape_fit(1, 1, 12000, 64) == 1      # 64-row tiles fit a 64 block
+    assert pm.tile_shape_fit(1, 2, 5000, 0) == 1        # 64-row super-tiles: 64-row tiles
+    assert pm.tile_shape_fit(1, 2, 8000, 0) == 2        # 128-row super-tiles
+    for nv in (2, 4, 8):                                # at most 64 rows: every block fits
+        for b in (64, 192, 320):
+            assert pm.tile_shape_fit(nv, 2, 12000, b) == 2
+    for D in range(1, 20000, 997):
+        for nv in (1, 2, 4, 8):
+            for sh in (0, 1, 2):
+                for b in (0, 64, 128, 192, 256, 448, 512):
+                    got = pm.tile_shape_fit(nv, sh, D, b)
+                    tr = 4 * (16 << got) // (2 * nv)
+                    edge = 256 if (D + 255) // 256 >= 45 else 128 if (D + 127) // 128 >= 45 else 64
+                    assert 0 <= got <= sh
+                    assert got == 0 or (tr <= edge and (b == 0 or b % tr == 0))
+    assert pm.tile_shape_fit(3, 0, 100, 0) == -1
+    assert pm.tile_shape_fit(1, 3, 100, 0) == -1
+    assert pm.tile_shape_fit(1, 0, 100, 100) == -1

@@ -222,3 +222,35 @@ def test_every_tile_shape_matches_oracle(pm, orc, nvec):
                 assert rel_l2(gb, ref) <= TOL_FP32, ("batch", strat, shape)
                 B.close()
             op.close()
+
+
+@pytest.mark.parametrize("b", [192, 256])
+def test_tall_tiles_stay_inside_cache_slots(pm, orc, b):
+    """One vector at tile shape 2 has 128-row tiles; D = 12000 (256-row
+    super-tiles) lets them run, and a partial cache of block size b reads
+    whole tiles from one slot only when 128 divides b: the library launches
+    shape 1 for b = 192 (procmv_tile_shape_fit) and shape 2 for b = 256.
+    Both against the binary64 oracle on sampled rows; the batched launch
+    with a cached b = 64 instance goes through the batch autotuner, which
+    tries every shape."""
+    import torch
+    D = 12000
+    assert pm.tile_shape_fit(1, 2, D, b) == (1 if b % 128 else 2)
+    X = workloads.gaussian_vectors(D, 1, seed=31)
+    rows = workloads.sampled_rows(D, 512, seed=32)
+    ref = orc.gue_apply_rows(13, D, X, rows=rows)
+    op = pm.Operator.gue(D, seed=13).plan(b, pm.PARTIAL, 0.5).set_tile_shape(2)
+    got = to_host(op.apply(to_dev(X)))[:, rows]
+    assert rel_l2(got, ref) <= TOL_FP32
+    ops = [op, pm.Operator.gue(700, seed=14).plan(64, pm.FULL, 1.0)]
+    B = pm.Batch(ops, 1)
+    Xb = np.concatenate([X[0], workloads.gaussian_vectors(700, 1, seed=33)[0]])
+    Xd = torch.from_numpy(Xb.astype(np.complex64)).cuda()
+    Yd = torch.empty_like(Xd)
+    B.autotune(Xd, Yd, reps=1)
+    B.apply(Xd, Yd)
+    Yb = to_host(Yd)
+    assert rel_l2(Yb[:D][rows], ref[0]) <= TOL_FP32
+    ref2 = orc.gue_apply_rows(14, 700, Xb[None, D:])
+    assert rel_l2(Yb[D:], ref2[0]) <= TOL_FP32
+    B.close()

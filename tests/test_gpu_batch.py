@@ -126,9 +126,44 @@ def test_c2_batch_shape_autotuned(pm, orc):
     B.apply(X, Y)
     got = _unpack(Y.cpu().numpy(), sizes, 4)
     Xs = _unpack(Xh, sizes, 4)
-    for k in np.argsort(sizes)[:3]:
-        ref = orc.gue_apply_rows(int(k) + 1, int(sizes[k]), Xs[k])
-        assert rel_l2(got[k], ref) <= 1e-5
+    # every instance against the binary64 oracle on 64 sampled rows (all four
+    # vectors), ragged sizes and several super-tile bands included
+    worst = 0.0
+    for k, D in enumerate(sizes):
+        rows = workloads.sampled_rows(int(D), 64, seed=1000 + k)
+        ref = orc.gue_apply_rows(k + 1, int(D), Xs[k], rows=rows)
+        err = rel_l2(got[k][:, rows], ref)
+        worst = max(worst, err)
+        assert err <= 1e-5, (k, int(D), err)
+    print(f"C2: worst sampled rel-L2 over 256 instances {worst:.2e}")
+
+
+def test_c2_graph_propagation_100_steps(pm, orc):
+    """The C2 batch (256 instances, 4 vectors) propagated 100 steps of
+    dt = 0.05 through the captured HIP graph; eight instances (the six
+    smallest and two near the median size) against the oracle's binary64
+    propagation of the same entries, every instance's norms conserved."""
+    import torch
+    sizes = workloads.batch_sizes(256)
+    ops = [pm.Operator.gue(int(D), seed=k + 1).plan(256) for k, D in enumerate(sizes)]
+    B = pm.Batch(ops, 4)
+    p0 = _packed(sizes, 4, seed=300).astype(np.complex64)
+    P = torch.from_numpy(p0).cuda()
+    dt, c, R, steps = 0.05, 0.0, 2.5, 100
+    nrm = B.propagate(P, dt, steps, c, R, graph=True, norms=True)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(nrm - 1.0)) < 1e-4
+    got = _unpack(P.cpu().numpy(), sizes, 4)
+    start = _unpack(p0, sizes, 4)
+    order = np.argsort(sizes)
+    pick = list(order[:6]) + list(order[127:129])
+    K = ch.cheb_order(R * dt)
+    for k in pick:
+        H = orc.gue_dense(int(k) + 1, int(sizes[k]))
+        ref = ch.propagate(lambda v: v @ H.T, start[k], c, R, dt, K, nsteps=steps)
+        err = rel_l2(got[k], ref)
+        print(f"instance {int(k)} D={int(sizes[k])}: rel-L2 vs binary64 {err:.2e}")
+        assert err < 1e-4
 
 
 @pytest.mark.parametrize("strat,f", [(0, 0.0), (1, 0.5), (2, 1.0)])

@@ -1,0 +1,181 @@
+"""GPU parity of the compensated binary32 arithmetic of the sinc-DVR operator
+(precision FP32_COMPENSATED) against the binary64 oracle.
+
+The compensated products apply the same binary32 entries as the plain ones
+(the band |i - j| < 64 in difference form, the rest of the row as a per-row
+constant); the Chebyshev recurrence carries hi + lo binary32 vectors.  The
+oracle evaluates the same entries in binary64 (row by row, or by FFT
+convolution for the long propagations), so every error below is the error of
+the GPU arithmetic; the harmonic-oscillator runs are also checked against
+the exact coherent state.  Tolerances: products rel-L2 1e-5; propagation
+1e-4 after 200 steps, scaled by sqrt(n/200) for n steps (rounding errors of
+independent steps add in quadrature).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import chebyshev as ch
+from paper_2606_31598_amd import workloads
+from tests.gpu_util import rel_l2, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "dvr_D32768_fp64.json")
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_31598_amd import procmv
+    procmv.load()
+    return procmv
+
+
+def step_budget(n):
+    return 1e-4 * np.sqrt(n / 200.0)
+
+
+@pytest.mark.parametrize("D,nv,strategy,f", [
+    (2, 1, 0, 0.0), (40, 2, 0, 0.0), (65, 1, 2, 1.0), (700, 1, 0, 0.0),
+    (1024, 3, 0, 0.0), (1500, 2, 1, 0.5), (1500, 4, 2, 1.0), (3000, 8, 1, 0.5),
+    (8192, 1, 0, 0.0)])
+def test_compensated_products_match_oracle(pm, orc, D, nv, strategy, f):
+    """Random and smooth vectors, every storage mode, the Toeplitz kernel,
+    the VALU tile kernel and (4+ cached vectors) the matrix cores."""
+    op = pm.Operator.dvr(D).plan(128, strategy, f, precision=pm.FP32_COMPENSATED)
+    d = orc.DVR(D)
+    X = workloads.gaussian_vectors(D, nv, seed=D + nv).astype(np.complex64)
+    got = to_host(op.apply(to_dev(X)))
+    ref = d.apply_rows(X)
+    err = rel_l2(got, ref)
+    Xs = np.repeat(workloads.wavepacket(D).astype(np.complex64), nv, axis=0)
+    got_s = to_host(op.apply(to_dev(Xs)))
+    err_s = rel_l2(got_s, d.apply_rows(Xs))
+    print(f"D={D} nv={nv} strategy={strategy} random {err:.2e} smooth {err_s:.2e}")
+    assert err < 1e-5
+    assert err_s < 1e-5
+
+
+def test_compensated_smooth_product_beats_plain(pm, orc):
+    """At D = 8192 the plain binary32 product of the wavepacket loses most of
+    its digits to the cancellation of the kinetic stencil (about 3e-3
+    rel-L2); the compensated one stays within the product tolerance."""
+    D = 8192
+    d = orc.DVR(D)
+    X = workloads.wavepacket(D).astype(np.complex64)
+    ref = d.apply_rows(X)
+    plain = to_host(pm.Operator.dvr(D).plan(256).apply(to_dev(X)))
+    comp = to_host(pm.Operator.dvr(D).plan(256, precision=pm.FP32_COMPENSATED)
+                   .apply(to_dev(X)))
+    e_plain, e_comp = rel_l2(plain, ref), rel_l2(comp, ref)
+    print(f"D={D} plain {e_plain:.2e} compensated {e_comp:.2e}")
+    assert e_comp < 1e-5 < e_plain
+
+
+@pytest.mark.parametrize("D,steps", [(1024, 200), (4096, 20)])
+def test_compensated_propagation_matches_oracle(pm, orc, D, steps):
+    dt = 0.05
+    op = pm.Operator.dvr(D).plan(256, precision=pm.FP32_COMPENSATED)
+    d = orc.DVR(D)
+    e0, e1 = d.spectral_bounds()
+    c, R = 0.5 * (e0 + e1), 0.5 * (e1 - e0)
+    psi0 = workloads.wavepacket(D).astype(np.complex64)
+    P = to_dev(psi0)
+    norms = op.propagate(P, dt, nsteps=steps, c=c, R=R, norms=True)
+    got = to_host(P)
+    K = ch.cheb_order(R * dt)
+    ref = ch.propagate(lambda v: d.apply_fft(v), psi0, c, R, dt, K, nsteps=steps)
+    exact = ch.coherent_state(d.x, steps * dt, 3.0, d.dx)[None, :]
+    e_ref, e_ex = rel_l2(got, ref), rel_l2(got, exact)
+    print(f"D={D} steps={steps} K={K} vs fp64 {e_ref:.2e} vs exact {e_ex:.2e} "
+          f"norm-1 {norms[-1, 0] - 1:.1e}")
+    assert e_ref < step_budget(steps)
+    assert e_ex < step_budget(steps)
+    assert np.max(np.abs(norms - 1.0)) < step_budget(steps)
+
+
+@pytest.mark.parametrize("strategy,f", [(0, 0.0), (1, 0.5), (2, 1.0)])
+def test_compensated_propagation_storage_modes(pm, orc, strategy, f):
+    """Procedural (Toeplitz kernel), half-cached and fully cached (tile
+    kernels), two vectors, ragged D."""
+    D, dt, steps = 1500, 0.05, 10
+    op = pm.Operator.dvr(D).plan(256, strategy, f, precision=pm.FP32_COMPENSATED)
+    d = orc.DVR(D)
+    e0, e1 = d.spectral_bounds()
+    c, R = 0.5 * (e0 + e1), 0.5 * (e1 - e0)
+    psi0 = np.concatenate([workloads.wavepacket(D),
+                           workloads.wavepacket(D, x0=-2.0)]).astype(np.complex64)
+    P = to_dev(psi0)
+    op.propagate(P, dt, nsteps=steps, c=c, R=R)
+    got = to_host(P)
+    ref = ch.propagate(lambda v: d.apply_fft(v), psi0, c, R, dt, ch.cheb_order(R * dt),
+                       nsteps=steps)
+    err = rel_l2(got, ref)
+    print(f"strategy={strategy} f={f} vs fp64 {err:.2e}")
+    assert err < step_budget(steps)
+
+
+def test_compensated_filter_matches_oracle(pm, orc):
+    D, tau = 1024, 0.5
+    op = pm.Operator.dvr(D).plan(256, precision=pm.FP32_COMPENSATED)
+    d = orc.DVR(D)
+    e0, e1 = d.spectral_bounds()
+    c, R = 0.5 * (e0 + e1), 0.5 * (e1 - e0)
+    psi0 = workloads.wavepacket(D).astype(np.complex64)
+    P = to_dev(psi0)
+    nrm = op.filter(P, tau, c=c, R=R, norms=True)
+    got = to_host(P)
+    z = R * tau
+    ref = ch.imag_time_filter(lambda v: d.apply_fft(v), psi0, c, R, tau,
+                              ch.filter_order(z))
+    err = rel_l2(got, ref)
+    print(f"filter D={D} tau={tau} vs fp64 {err:.2e}")
+    assert err < 1e-5
+    assert abs(nrm[0] - np.linalg.norm(ref)) < 1e-5 * np.linalg.norm(ref)
+
+
+def test_compensated_benchmark_configuration(pm, orc):
+    """The benchmark's configuration at full size: sinc-DVR D = 32768,
+    dt = 0.05, K = 83,108 products per step, procedural, library bounds.
+    After 2 steps the state is compared with the binary64 oracle's state
+    (FFT-Toeplitz products of the same entries, stored by
+    tests/golden/make_dvr_full_size.py) on 64 grid points and, through the
+    triangle inequality, in rel-L2 via the exact coherent state; after 8
+    steps with the exact state against the scaled budget."""
+    D, dt = 32768, 0.05
+    op = pm.Operator.dvr(D).plan(256, pm.PROCEDURAL, precision=pm.FP32_COMPENSATED)
+    c, R = op.spectral_bounds()
+    K = pm.cheb_order(R * dt, 1e-10)
+    d = orc.DVR(D)
+    g = json.load(open(GOLDEN))
+    assert g["D"] == D and g["K"] == ch.cheb_order(g["R"] * dt, 1e-10)
+    P = to_dev(workloads.wavepacket(D))
+    done = 0
+    for rec in g["steps"]:
+        op.propagate(P, dt, nsteps=rec["step"] - done, K=K, c=c, R=R)
+        done = rec["step"]
+        got = to_host(P)
+        exact = ch.coherent_state(d.x, done * dt, 3.0, d.dx)[None, :]
+        e_ex = rel_l2(got, exact)
+        ref_s = np.array([complex(a, b) for a, b in rec["sample"]])
+        e_s = float(np.max(np.abs(got[0, g["sample_index"]] - ref_s)) /
+                    np.max(np.abs(ref_s)))
+        print(f"step {done}: vs exact {e_ex:.2e}; fp64 vs exact {rec['fp64_vs_exact']:.2e}; "
+              f"sampled max rel vs fp64 {e_s:.2e}")
+        # rel-L2 against the binary64 state is at most e_ex + fp64_vs_exact
+        assert e_ex + rec["fp64_vs_exact"] < step_budget(done)
+        assert e_s < step_budget(done)
+    n = 8
+    norms = op.propagate(P, dt, nsteps=n - done, K=K, c=c, R=R, norms=True)
+    got = to_host(P)
+    exact = ch.coherent_state(d.x, n * dt, 3.0, d.dx)[None, :]
+    e_ex = rel_l2(got, exact)
+    print(f"step {n}: vs exact {e_ex:.2e} norm-1 {norms[-1, 0] - 1:.1e}")
+    assert e_ex < step_budget(n)
+    assert abs(norms[-1, 0] - 1.0) < step_budget(n)

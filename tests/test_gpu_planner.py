@@ -51,6 +51,44 @@ def test_mlp_gradients_match_oracle(pm):
         assert np.allclose(g32[sl], ref[sl], rtol=1e-3, atol=1e-6 * np.abs(ref).max())
 
 
+def _unpack(v):
+    sizes = (("W1", (8, 64)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)),
+             ("W3", (64, 1)), ("b3", (1,)))
+    out, o = {}, 0
+    for k, shp in sizes:
+        n = int(np.prod(shp))
+        out[k] = np.asarray(v[o:o + n], np.float64).reshape(shp)
+        o += n
+    return out
+
+
+def test_mlp_adam_steps_match_oracle(pm):
+    """procmv_mlp_train after 1, 2 and 3 full-batch steps against the
+    oracle's Adam update (Kingma & Ba; lr 3e-3, betas 0.9/0.999, eps 1e-8),
+    element by element.  Both sides take the same binary32 gradient (the
+    library's own, procmv_mlp_grad at the GPU's current parameters), so the
+    comparison is of the update rule and its bias correction, not of the
+    gradient arithmetic (checked above against binary64)."""
+    rng = np.random.default_rng(11)
+    z = rng.standard_normal((200, 8))
+    t = rng.standard_normal(200)
+    p0 = _pack(opl.mlp_init(seed=4)).astype(np.float32)
+    lr = 3e-3
+    ref = _unpack(p0)
+    m = {k: np.zeros_like(a) for k, a in ref.items()}
+    v = {k: np.zeros_like(a) for k, a in ref.items()}
+    prev = p0
+    for step in (1, 2, 3):
+        g32, _ = pm.mlp_grad(prev, z, t)
+        opl.adam_step(ref, _unpack(g32), m, v, step, lr=lr)
+        got, _ = pm.mlp_train(z, t, p0, step, lr)
+        want = _pack(ref)
+        # lr-sized moves of parameters of order 0.1-1: binary32 rounding of
+        # the update and of the parameters
+        assert np.allclose(got, want, rtol=1e-5, atol=1e-7), step
+        prev = got
+
+
 def test_mlp_training_fits(pm):
     rng = np.random.default_rng(3)
     x = rng.uniform(-1, 1, (512, 8))
@@ -121,3 +159,40 @@ def test_measure_reports_fill_and_product_times(pm):
     tf1, ta1 = pm.measure(pm.GEN_PHILOX_GUE, D, 1, 256, pm.FULL, 1.0, reps=2)
     assert tf0 == 0.0 and ta0 > 0 and ta5 > 0 and ta1 > 0
     assert 0 < tf5 < tf1
+
+
+@pytest.mark.parametrize("which", [2, 3])
+def test_plan_auto_measured_and_hybrid(pm, orc, which):
+    """procmv_plan_auto with local measurement: planner 2 (Algorithm 2)
+    times the analytic ranking's K_bench best plans, planner 3 (Algorithm 3,
+    hybrid) the learned ranking's; the chosen plan is one of those K_bench,
+    re-measuring them here puts it within the timing noise of the fastest,
+    and the planned operator's product matches the binary64 oracle."""
+    import torch
+    model_path = os.path.join(DATA, "mi355x_planner_mlp.json")
+    trials = os.path.join(DATA, "mi355x_plan_trials.jsonl")
+    if not (os.path.exists(trials) and os.path.exists(model_path)):
+        pytest.skip("no measured plan trials / trained model committed")
+    from paper_2606_31598_amd import planner, workloads
+    mm, params, norm = planner.load_planners(trials, model_path)
+    D, nv, budget, reuse = 6000, 2, 64e9, 50
+    order, _ = pm.plan_rank(0 if which == 2 else 1, D, nv, budget, reuse, 0, mm=mm,
+                            params=params, norm=norm)
+    top = order[:4]
+    op = pm.Operator.gue(D, seed=5)
+    idx = op.plan_auto(nv, budget, reuse, planner=which, mm=mm, params=params, norm=norm)
+    assert idx in top
+    cands = pm.plan_candidates()
+    total = {}
+    for q in top:
+        b, st, f = cands[q]
+        tf, ta = pm.measure(pm.GEN_PHILOX_GUE, D, nv, b, st, f, seed=5, warmup=1, reps=3)
+        total[q] = tf + reuse * ta
+    print(which, idx, {q: round(t, 3) for q, t in total.items()})
+    assert total[idx] <= 1.25 * min(total.values())
+    X = workloads.gaussian_vectors(D, nv, seed=12)
+    got = op.apply(torch.from_numpy(X.astype(np.complex64)).cuda()).cpu().numpy()
+    assert rel_l2(got, orc.gue_apply_rows(5, D, X)) <= 1e-5
+    op.close()
+    with pytest.raises(pm.ProcmvError):
+        pm.plan_choose(which, D, nv, budget, reuse, 0, mm=mm)

@@ -8,6 +8,7 @@ an FFT-based Toeplitz product and the harmonic-oscillator spectrum n + 1/2.
 import numpy as np
 import pytest
 
+from oracle import chebyshev as ch
 from paper_2606_31598_amd import workloads
 
 
@@ -103,3 +104,36 @@ def test_dvr_entries_closed_form(orc):
     assert np.allclose(d.v64, 0.5 * d.x ** 2, rtol=1e-15)
     assert np.isclose(d.d0, np.pi ** 2 / (6 * dx * dx), rtol=1e-15)
     assert np.array_equal(d.tk32, d.tk64.astype(np.float32))
+
+
+@pytest.mark.parametrize("D", [2, 3, 64, 777, 4096])
+def test_dvr_fft_product_matches_rows(orc, D):
+    """The oracle's FFT-Toeplitz product (used for long propagations) equals
+    the row-by-row binary64 product of the same entries, rounded and exact
+    tables, and is Hermitian: <x, H y> = <H x, y>."""
+    d = orc.DVR(D)
+    X = workloads.gaussian_vectors(D, 2, seed=D)
+    for rounded in (True, False):
+        a = d.apply_fft(X, rounded=rounded)
+        b = d.apply_rows(X, rounded=rounded)
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-13
+    Hx = d.apply_fft(X[:1])
+    Hy = d.apply_fft(X[1:])
+    lhs = np.vdot(X[0], Hy[0])
+    rhs = np.vdot(Hx[0], X[1])
+    assert abs(lhs - rhs) < 1e-12 * np.linalg.norm(Hx) * np.linalg.norm(X[1])
+
+
+def test_dvr_fft_propagation_matches_dense(orc):
+    """Chebyshev propagation through the FFT product equals the one through
+    the dense binary64 matrix (same entries) to rounding."""
+    D, dt, steps = 512, 0.05, 5
+    d = orc.DVR(D)
+    H = d.dense()
+    e0, e1 = d.spectral_bounds()
+    c, R = (e0 + e1) / 2, (e1 - e0) / 2
+    K = ch.cheb_order(R * dt)
+    psi = workloads.wavepacket(D)
+    a = ch.propagate(lambda v: d.apply_fft(v), psi, c, R, dt, K, nsteps=steps)
+    b = ch.propagate(lambda v: v @ H.T, psi, c, R, dt, K, nsteps=steps)
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-12
