@@ -125,6 +125,26 @@ procmv_status procmv_plan(procmv_op_t H, int32_t block_size,
 procmv_status procmv_apply(procmv_op_t H, const void* X, int64_t ldx,
                            void* Y, int64_t ldy, int32_t nvec, void* stream);
 
+/* Allocation-free form of procmv_apply, for callers that cannot allocate
+ * device memory during the call (code under HIP stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, kernels
+ * and results as procmv_apply (bit-identical outputs), but the partial slots
+ * of the product live in a static device workspace of 64 MiB that the
+ * library's code object holds on every device it runs on until the process
+ * ends, instead of the operator's own buffer; the call allocates and frees
+ * nothing and records no timing events (procmv_profile_enable does not
+ * cover it).  The operator must already be created and planned (those calls
+ * allocate).  Every call on one device shares that device's workspace and
+ * overwrites it (every partial slot is written before it is read, so no
+ * clearing is needed): calls that overlap on one device, on different
+ * streams or threads, race and give wrong results.  PROCMV_ERR_INVALID_ARG
+ * when a vector block's partial slots (slots x vectors per launch x D x 8
+ * bytes: e.g. 8.4 MB for the procedural sinc-DVR operator at D = 32768 and
+ * one vector, 33.8 MB per vector for a Philox-GUE operator at D = 32768)
+ * exceed the workspace, and for the argument errors of procmv_apply. */
+procmv_status procmv_apply_noalloc(procmv_op_t H, const void* X, int64_t ldx,
+                                   void* Y, int64_t ldy, int32_t nvec, void* stream);
+
 /* Default spectral bounds used by procmv_chebyshev_propagate when spec_R is
  * not positive: GUE c = 0, R = 2.5 (semicircle edge 2 plus margin); DVR
  * E_min = 0, E_max = pi^2/(2 mass dx^2) + max V. */

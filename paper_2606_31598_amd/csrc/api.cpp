@@ -753,6 +753,19 @@ procmv_status procmv_apply(procmv_op_t H, const void* X, int64_t ldx, void* Y,
     return apply_impl(H, X, ldx, Y, ldy, nvec, stream, Scratch{});
 }
 
+procmv_status procmv_apply_noalloc(procmv_op_t H, const void* X, int64_t ldx, void* Y,
+                                   int64_t ldy, int32_t nvec, void* stream)
+{
+    // the device-resident static workspace of the current device (its
+    // address is resolved once per device; no allocation here)
+    Scratch scr;
+    size_t bytes = 0;
+    void* p = nullptr;
+    HIP_TRY(static_workspace(&p, &bytes));
+    scr.p = (float2*)p;
+    scr.bytes = bytes;
+    return apply_impl(H, X, ldx, Y, ldy, nvec, stream, scr);
+}
 
 procmv_status procmv_spectral_bounds(procmv_op_t H, double* c, double* R)
 {

@@ -211,6 +211,11 @@ hipError_t launch_tile_apply(const TileArgs& a, int nv, int shape, int n_st,
 hipError_t launch_tile_apply_batched(const BatchTileLaunch& b, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, Epi mode, hipStream_t s,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// Static device workspace of the allocation-free product (defined in
+// noalloc.hip): the current device's copy of a file-scope array, its
+// address resolved once per device.
+size_t static_workspace_bytes();
+hipError_t static_workspace(void** ptr, size_t* bytes);
 // Compensated reduction of the sinc-DVR operator (defined in comp.hip).
 hipError_t launch_reduce_comp(const ReduceArgs& a, Epi mode, hipStream_t s,
                               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);

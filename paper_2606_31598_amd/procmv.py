@@ -34,7 +34,7 @@ EXPORTS = [
     "procmv_plan_features", "procmv_plan_model_time", "procmv_plan_choose",
     "procmv_plan_auto", "procmv_mlp_param_count", "procmv_mlp_grad",
     "procmv_mlp_train", "procmv_mlp_predict", "procmv_set_tile_shape",
-    "procmv_tile_shape_fit", "procmv_plan_rank",
+    "procmv_tile_shape_fit", "procmv_apply_noalloc", "procmv_plan_rank",
     "procmv_set_dvr_kernel",
 ]
 
@@ -83,6 +83,7 @@ def load():
                                          c.POINTER(vp)]
     L.procmv_plan.argtypes = [vp, c.c_int32, c.c_int, c.c_double, c.c_int, vp]
     L.procmv_apply.argtypes = [vp, vp, c.c_int64, vp, c.c_int64, c.c_int32, vp]
+    L.procmv_apply_noalloc.argtypes = [vp, vp, c.c_int64, vp, c.c_int64, c.c_int32, vp]
     L.procmv_spectral_bounds.argtypes = [vp, c.POINTER(c.c_double),
                                          c.POINTER(c.c_double)]
     L.procmv_cheb_order.argtypes = [c.c_double, c.c_double]
