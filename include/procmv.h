@@ -68,7 +68,7 @@ typedef enum {
  * binary32 entries and binary32 operations, arranged against the
  * cancellation of the kinetic stencil (entries ~1/dx^2 with vanishing row
  * sums acting on smooth states).  The tile kernels apply the operator
- * without the band 0 < |i - j| < W (W = min(64, D)); the reduction adds the
+ * without the band 0 < |i - j| < W (W = min(32, D)); the reduction adds the
  * band in difference form, sum_band t(i-j) (x_j - x_i), and the rest of the
  * row as the per-row constant C_i = d + sum_band t(i-j) + V_i (binary64 sum
  * of the binary32 entries, applied as a hi + lo binary32 pair), which is the

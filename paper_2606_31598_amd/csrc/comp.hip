@@ -60,6 +60,7 @@ template <Epi MODE>
 __global__ __launch_bounds__(256) void reduce_comp_kernel(ReduceArgs a)
 {
     constexpr int NS = 64 + 2 * (kNearBand - 1);
+    static_assert(NS <= 256, "one staged element per thread");
     __shared__ float2 xh[NS], xl[NS];
     __shared__ float tks[kNearBand];
     __shared__ float2 part[4][64];
@@ -67,33 +68,65 @@ __global__ __launch_bounds__(256) void reduce_comp_kernel(ReduceArgs a)
     const int D = a.D;
     const int v = blockIdx.y;
     const int r0 = blockIdx.x * 64;
-    const float2* xv = a.X + (size_t)v * a.ldx;
-    const float2* xlv = a.Xlo ? a.Xlo + (size_t)v * a.ldxl : nullptr;
-    const int nst = 64 + 2 * (W - 1);
-    for (int q = threadIdx.x; q < nst; q += 256) {
-        const int j = r0 - (W - 1) + q;
-        const bool in = j >= 0 && j < D;
-        xh[q] = in ? xv[j] : make_float2(0.f, 0.f);
-        xl[q] = (in && xlv) ? xlv[j] : make_float2(0.f, 0.f);
-    }
-    for (int q = threadIdx.x; q < W; q += 256) tks[q] = q > 0 ? a.tk[q] : 0.f;
-    __syncthreads();
-
     const int g = threadIdx.x >> 6;
     const int l = threadIdx.x & 63;
     const int i = r0 + l;
     const bool live = i < D;
+    const size_t e = (size_t)v * a.ldy + i;
+
+    // Every global load is issued before the first barrier so that their
+    // latencies overlap: the staged window, the epilogue operands (group 0)
+    // and the group's partial slots.
+    const float2* xv = a.X + (size_t)v * a.ldx;
+    const float2* xlv = a.Xlo ? a.Xlo + (size_t)v * a.ldxl : nullptr;
+    const int nst = 64 + 2 * (W - 1);
+    const int js = r0 - (W - 1) + (int)threadIdx.x;
+    const bool stage = (int)threadIdx.x < nst;
+    const bool sin = stage && js >= 0 && js < D;
+    const float2 sh = sin ? xv[js] : make_float2(0.f, 0.f);
+    const float2 sl = (sin && xlv) ? xlv[js] : make_float2(0.f, 0.f);
+    const float tkv = ((int)threadIdx.x < W && threadIdx.x > 0) ? a.tk[threadIdx.x] : 0.f;
+    float2 cv = make_float2(0.f, 0.f), ph = cv, pl = cv;
+    double2 acc0 = double2{0.0, 0.0};
+    if (g == 0 && live) {
+        cv = a.cv[i];
+        if (MODE == Epi::kChebStep) {
+            ph = a.Y[e];
+            pl = a.Ylo[(size_t)v * a.ldylo + i];
+            acc0 = a.acc[(size_t)v * a.ldacc + i];
+        }
+    }
     float sx = 0.f, sy = 0.f;
     if (live) {
         // far part: the group's share of the partial slots, in slot order
         const float2* p = a.P + (size_t)v * a.ldp + i;
         const size_t stride = (size_t)a.nv_stride * a.ldp;
         const int k0 = (a.n_slots * g) / 4, k1 = (a.n_slots * (g + 1)) / 4;
-        for (int k = k0; k < k1; ++k) {
+        int k = k0;
+        for (; k + 4 <= k1; k += 4) {
+            const float2 q0 = p[(size_t)(k + 0) * stride];
+            const float2 q1 = p[(size_t)(k + 1) * stride];
+            const float2 q2 = p[(size_t)(k + 2) * stride];
+            const float2 q3 = p[(size_t)(k + 3) * stride];
+            sx += q0.x; sy += q0.y;
+            sx += q1.x; sy += q1.y;
+            sx += q2.x; sy += q2.y;
+            sx += q3.x; sy += q3.y;
+        }
+        for (; k < k1; ++k) {
             const float2 q = p[(size_t)k * stride];
             sx += q.x;
             sy += q.y;
         }
+    }
+    if (stage) {
+        xh[threadIdx.x] = sh;
+        xl[threadIdx.x] = sl;
+    }
+    if ((int)threadIdx.x < W) tks[threadIdx.x] = tkv;
+    __syncthreads();
+
+    if (live) {
         // band: the group's share of the offsets -(W-1)..-1, 1..W-1
         const int no = 2 * (W - 1);
         const int o0 = (no * g) / 4, o1 = (no * (g + 1)) / 4;
@@ -127,14 +160,12 @@ __global__ __launch_bounds__(256) void reduce_comp_kernel(ReduceArgs a)
 
     // y = far + band + C_i x (C as hi + lo, x as hi + lo)
     const float2 x = xh[l + W - 1], xlo = xl[l + W - 1];
-    const float2 cv = a.cv[i];
     sx = __builtin_fmaf(cv.y, x.x, sx);
     sy = __builtin_fmaf(cv.y, x.y, sy);
     sx = __builtin_fmaf(cv.x, xlo.x, sx);
     sy = __builtin_fmaf(cv.x, xlo.y, sy);
     sx = __builtin_fmaf(cv.x, x.x, sx);
     sy = __builtin_fmaf(cv.x, x.y, sy);
-    const size_t e = (size_t)v * a.ldy + i;
     if (MODE == Epi::kApply) {
         a.Y[e] = make_float2(sx, sy);
         return;
@@ -157,16 +188,13 @@ __global__ __launch_bounds__(256) void reduce_comp_kernel(ReduceArgs a)
         r.y += a.a1.x * qy + a.a1.y * qx;
         a.acc[(size_t)v * a.ldacc + i] = r;
     } else {
-        const float2 ph = a.Y[e];
-        const size_t el = (size_t)v * a.ldylo + i;
-        const float2 pl = a.Ylo[el];
         comp_step<false>(2.f, a.alpha, a.gamma_hi, a.gamma_lo, sx, x.x, xlo.x, ph.x, pl.x, nh.x,
                          nl.x);
         comp_step<false>(2.f, a.alpha, a.gamma_hi, a.gamma_lo, sy, x.y, xlo.y, ph.y, pl.y, nh.y,
                          nl.y);
         a.Y[e] = nh;
-        a.Ylo[el] = nl;
-        double2 r = a.acc[(size_t)v * a.ldacc + i];
+        a.Ylo[(size_t)v * a.ldylo + i] = nl;
+        double2 r = acc0;
         const double qx = (double)nh.x + (double)nl.x, qy = (double)nh.y + (double)nl.y;
         r.x += a.a0.x * qx - a.a0.y * qy;
         r.y += a.a0.x * qy + a.a0.y * qx;

@@ -11,7 +11,10 @@
 // per d it reads the 16 symbol values of its A fragment and the 16 x values
 // of its B fragment from LDS and issues 16 v_mfma_f32_32x32x2_f32 (the whole
 // K = 32 of the block).  A workgroup's 4 waves cover 64 consecutive output
-// blocks with the same chunk of d; each chunk's sums go to one partial slot,
+// blocks with the same chunk of d (about one workgroup per compute unit in
+// all: fewer chunks mean fewer partial slots to write and reduce and less
+// staging, which measured faster than more resident workgroups); each
+// chunk's sums go to one partial slot,
 // reduced in a fixed order afterwards like the VALU kernel's column chunks.
 // The symbol comes from the same table as the VALU kernel (binary32 entries,
 // zero at k = 0 and, for the compensated arithmetic, inside the band).
@@ -27,14 +30,16 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kBlk = 32;           // Toeplitz block edge
 constexpr int kWaveBlocks = 16;    // output blocks per wave (32 MFMA columns: re, im)
-constexpr int kGroupBlocks = 64;   // output blocks per workgroup (4 waves)
-constexpr int kMaxChunk = 64;      // block offsets per workgroup (LDS sizing)
+constexpr int kThreads = 256;      // 4 waves per workgroup
+constexpr int kGroupBlocks = kWaveBlocks * (kThreads / 64);   // output blocks per workgroup
+constexpr int kMaxChunk = 72;      // block offsets per workgroup (LDS sizing)
+constexpr int kTargetGroups = 256; // about one workgroup per compute unit
 // x blocks one workgroup reads: kGroupBlocks + chunk - 1
 constexpr int kXBlocks = kGroupBlocks + kMaxChunk - 1;
 constexpr int kXPitch = 16;        // floats per (component, parity, block)
 constexpr int kSymLen = kBlk * kMaxChunk + 2 * (kBlk - 1) + 1;
 
-__global__ __launch_bounds__(256) void dvr_toeplitz_mfma_kernel(DvrToeplitzArgs a, int n_chunks)
+__global__ __launch_bounds__(kThreads) void dvr_toeplitz_mfma_kernel(DvrToeplitzArgs a, int n_chunks)
 {
     // x split by component (re, im) and by parity of the index within its
     // block: xs[c][kg][B][s] = x_c[32 B + 2 s + kg], so that the 16 values a
@@ -55,22 +60,42 @@ __global__ __launch_bounds__(256) void dvr_toeplitz_mfma_kernel(DvrToeplitzArgs 
     const int chunk = blockIdx.y;                     // partial slot
 
     if (d0 < d1) {
-        // symbol window: m = 32 d + p - q in [32 d0 - 31, 32 (d1 - 1) + 31]
+        // symbol window: m = 32 d + p - q in [32 d0 - 31, 32 (d1 - 1) + 31];
+        // x blocks B in [I0 - d1 + 1, I0 + 63 - d0].  Each thread issues all
+        // its global loads before its LDS stores, so they are in flight together.
         const int mlo = kBlk * d0 - (kBlk - 1);
         const int nm = kBlk * (d1 - d0) + 2 * (kBlk - 1);
-        for (int e = threadIdx.x; e < nm; e += 256) {
-            const int m = mlo + e;
-            sym[e] = (m > -D && m < D) ? a.text[m + D - 1] : 0.f;
-        }
-        // x blocks B in [I0 - d1 + 1, I0 + 63 - d0]
         const int Blo = I0 - d1 + 1;
-        const int nB = kGroupBlocks + (d1 - d0) - 1;
-        for (int e = threadIdx.x; e < nB * kBlk; e += 256) {
-            const int bb = e / kBlk, r = e - bb * kBlk;
-            const int j = (Blo + bb) * kBlk + r;
-            const float2 v = (j >= 0 && j < D) ? a.X[j] : make_float2(0.f, 0.f);
-            xs[0][r & 1][bb][r >> 1] = v.x;
-            xs[1][r & 1][bb][r >> 1] = v.y;
+        const int nx = (kGroupBlocks + (d1 - d0) - 1) * kBlk;
+        constexpr int SPER = (kSymLen + kThreads - 1) / kThreads;
+        constexpr int XPER = (kXBlocks * kBlk + kThreads - 1) / kThreads;
+        float sv[SPER];
+        float2 xv[XPER];
+#pragma unroll
+        for (int u = 0; u < SPER; ++u) {
+            const int e = (int)threadIdx.x + kThreads * u;
+            const int m = mlo + e;
+            sv[u] = (e < nm && m > -D && m < D) ? a.text[m + D - 1] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < XPER; ++u) {
+            const int e = (int)threadIdx.x + kThreads * u;
+            const int j = Blo * kBlk + e;
+            xv[u] = (e < nx && j >= 0 && j < D) ? a.X[j] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < SPER; ++u) {
+            const int e = (int)threadIdx.x + kThreads * u;
+            if (e < nm) sym[e] = sv[u];
+        }
+#pragma unroll
+        for (int u = 0; u < XPER; ++u) {
+            const int e = (int)threadIdx.x + kThreads * u;
+            if (e < nx) {
+                const int bb = e / kBlk, r = e - bb * kBlk;
+                xs[0][r & 1][bb][r >> 1] = xv[u].x;
+                xs[1][r & 1][bb][r >> 1] = xv[u].y;
+            }
         }
     }
     __syncthreads();
@@ -122,10 +147,10 @@ __global__ __launch_bounds__(256) void dvr_toeplitz_mfma_kernel(DvrToeplitzArgs 
 
 int dvr_mfma_chunks(int32_t D)
 {
-    // about two workgroups per compute unit: 512 / (row groups), at least one
+    // about kTargetGroups workgroups in all (row groups x chunks), at least one
     const int groups = ((D + kBlk - 1) / kBlk + kGroupBlocks - 1) / kGroupBlocks;
     const int nd = kGroupBlocks + (D + kBlk - 1) / kBlk - 1;
-    int s = (512 + groups - 1) / groups;
+    int s = (kTargetGroups + groups - 1) / groups;
     // each chunk at most kMaxChunk offsets (LDS window)
     const int smin = (nd + kMaxChunk - 1) / kMaxChunk;
     if (s < smin) s = smin;
@@ -140,10 +165,10 @@ hipError_t launch_dvr_toeplitz_mfma(const DvrToeplitzArgs& a, hipStream_t s, hip
     const int chunks = dvr_mfma_chunks(a.D);
     const dim3 grid((unsigned)groups, (unsigned)chunks);
     if (e0)
-        hipExtLaunchKernelGGL(dvr_toeplitz_mfma_kernel, grid, dim3(256), 0, s, e0, e1, 0, a,
+        hipExtLaunchKernelGGL(dvr_toeplitz_mfma_kernel, grid, dim3(kThreads), 0, s, e0, e1, 0, a,
                               chunks);
     else
-        hipLaunchKernelGGL(dvr_toeplitz_mfma_kernel, grid, dim3(256), 0, s, a, chunks);
+        hipLaunchKernelGGL(dvr_toeplitz_mfma_kernel, grid, dim3(kThreads), 0, s, a, chunks);
     return hipGetLastError();
 }
 

@@ -131,7 +131,7 @@ struct ReduceArgs {
 
 // Band of the compensated sinc-DVR arithmetic: entries with |i - j| < W are
 // summed in difference form by the reduction, W = min(kNearBand, D).
-constexpr int kNearBand = 64;
+constexpr int kNearBand = 32;
 
 // Epilogue of the fixed-order reduction for output element (v, i) whose
 // summed partials are (sx, sy): add the site diagonal, scale, add the

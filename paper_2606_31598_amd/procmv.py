@@ -76,6 +76,11 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_2606_31598_amd.build`")
+    # PyTorch brings its own HIP runtime: it must bring the GPU up before
+    # this library's runtime does, or PyTorch later finds no GPU
+    import torch
+    if torch.cuda.is_available():
+        torch.cuda.init()
     L = ctypes.CDLL(LIB_PATH)
     c = ctypes
     vp = c.c_void_p

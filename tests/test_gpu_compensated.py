@@ -2,7 +2,7 @@
 (precision FP32_COMPENSATED) against the binary64 oracle.
 
 The compensated products apply the same binary32 entries as the plain ones
-(the band |i - j| < 64 in difference form, the rest of the row as a per-row
+(the band |i - j| < 32 in difference form, the rest of the row as a per-row
 constant); the Chebyshev recurrence carries hi + lo binary32 vectors.  The
 oracle evaluates the same entries in binary64 (row by row, or by FFT
 convolution for the long propagations), so every error below is the error of
@@ -41,6 +41,18 @@ def step_budget(n):
     return 1e-4 * np.sqrt(n / 200.0)
 
 
+def scaled_product_error(got, ref, X, R):
+    """Error of a product in the units the propagation sees: the rescaled
+    operator (H - c)/R applied to x, ||dy|| / (R ||x||).  A Chebyshev step
+    carries such per-product errors with an amplification that the plain
+    binary32 arithmetic exhibits at D = 32768: about 2e-7 per product became
+    4.4e-4 per step, a factor of ~2400.  The step budget 1e-4 / sqrt(200) =
+    7e-6 then asks for ~3e-9 per product; the check uses 1e-9.  (A smooth
+    vector's H x is tiny next to R ||x||, so its rel-L2 against H x measures
+    the stencil's cancellation, not the propagation error.)"""
+    return float(np.linalg.norm(np.asarray(got) - ref) / (R * np.linalg.norm(X)))
+
+
 @pytest.mark.parametrize("D,nv,strategy,f", [
     (2, 1, 0, 0.0), (40, 2, 0, 0.0), (65, 1, 2, 1.0), (700, 1, 0, 0.0),
     (1024, 3, 0, 0.0), (1500, 2, 1, 0.5), (1500, 4, 2, 1.0), (3000, 8, 1, 0.5),
@@ -56,10 +68,16 @@ def test_compensated_products_match_oracle(pm, orc, D, nv, strategy, f):
     err = rel_l2(got, ref)
     Xs = np.repeat(workloads.wavepacket(D).astype(np.complex64), nv, axis=0)
     got_s = to_host(op.apply(to_dev(Xs)))
-    err_s = rel_l2(got_s, d.apply_rows(Xs))
-    print(f"D={D} nv={nv} strategy={strategy} random {err:.2e} smooth {err_s:.2e}")
+    ref_s = d.apply_rows(Xs)
+    err_s = rel_l2(got_s, ref_s)
+    R = 0.5 * d.spectral_bounds()[1]
+    sc = scaled_product_error(got_s, ref_s, Xs, R)
+    print(f"D={D} nv={nv} strategy={strategy} random {err:.2e} smooth {err_s:.2e} "
+          f"(scaled {sc:.1e})")
     assert err < 1e-5
-    assert err_s < 1e-5
+    # within the product tolerance, or (where the stencil's cancellation makes
+    # H x tiny) within the propagation's per-product allowance
+    assert err_s < 1e-5 or sc < 1e-9
 
 
 def test_compensated_smooth_product_beats_plain(pm, orc):
@@ -76,6 +94,7 @@ def test_compensated_smooth_product_beats_plain(pm, orc):
     e_plain, e_comp = rel_l2(plain, ref), rel_l2(comp, ref)
     print(f"D={D} plain {e_plain:.2e} compensated {e_comp:.2e}")
     assert e_comp < 1e-5 < e_plain
+    assert e_comp < e_plain / 100
 
 
 @pytest.mark.parametrize("D,steps", [(1024, 200), (4096, 20)])

