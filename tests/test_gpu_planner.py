@@ -124,6 +124,33 @@ def test_trained_planner_beats_fixed_plan(pm):
     assert res["learned"]["within_10pct"] >= res["procedural"]["within_10pct"]
 
 
+def test_planners_on_held_out_sizes(pm):
+    """The library's rankings (binary32 network inference on the GPU and the
+    analytic model) on 200 held-out workloads whose sizes and vector counts
+    lie outside the training grid, against a fresh exhaustive measurement:
+    the learned choice is within 10 % of the best measured plan on at least
+    90 % of them, the hybrid (learned top 4, best measured) does at least as
+    well, and both beat the analytic choice and the fixed procedural plan in
+    mean regret."""
+    heldout = os.path.join(DATA, "mi355x_plan_heldout.jsonl")
+    trials = os.path.join(DATA, "mi355x_plan_trials.jsonl")
+    model_path = os.path.join(DATA, "mi355x_planner_mlp.json")
+    if not all(os.path.exists(f) for f in (heldout, trials, model_path)):
+        pytest.skip("no held-out trials / trained model committed")
+    from paper_2606_31598_amd import planner
+    mm, _ = planner.load_trials(trials)
+    _, table = planner.load_trials(heldout)
+    res = planner.evaluate_heldout(table, mm, json.load(open(model_path)))
+    print(json.dumps(res))
+    assert res["n_workloads"] == 200
+    lr, hy = res["learned"], res["hybrid"]
+    assert lr["within_10pct"] >= 0.90 and lr["mean_regret"] < 0.10
+    assert hy["within_10pct"] >= lr["within_10pct"]
+    for other in ("analytic", "procedural"):
+        assert lr["mean_regret"] < res[other]["mean_regret"]
+        assert hy["mean_regret"] < res[other]["mean_regret"]
+
+
 def test_plan_auto_learned_and_analytic(pm, orc):
     """procmv_plan_auto plans the candidate procmv_plan_choose ranks first,
     and the planned operator's product matches the binary64 oracle."""
