@@ -8,7 +8,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libprocmv.so")
 SOURCES = ["api.cpp", "apply.hip", "cheb.hip", "dvr.hip", "mfma.hip", "batch.hip", "mlp.hip",
            "selftest.hip", "lanczos.hip", "kron.hip", "comp.hip",
-           "noalloc.hip", "dvr_mfma.hip"]
+           "noalloc.hip", "dvr_mfma.hip", "dvr_bf16.hip"]
 
 # -ffp-contract=off: the generators are fixed sequences of binary32 operations
 # and every fused multiply-add in the kernels is written out explicitly.

@@ -78,7 +78,8 @@ struct procmv_op {
     int32_t b = 0, n_blk = 0;
     int strategy = 0, precision = 0;
     int tile_shape = -1;      // VALU tile shape (see launch_tile_apply); -1 = per class
-    int dvr_kernel = 0;       // procedural sinc-DVR product: 0 auto, 1 VALU, 2 matrix cores
+    int dvr_kernel = 0;       // procedural sinc-DVR product: 0 auto, 1 VALU, 2 binary32
+                              // matrix cores, 3 split-bf16 matrix cores
     double frac = 0.0;
     int64_t n_pair = 0, p_cache = 0;
     int32_t* d_pair_slot = nullptr;
@@ -400,9 +401,11 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
     // one vector of a large operator: the Toeplitz blocks on the matrix cores
     const bool tmfma = toeplitz && nv == 1 &&
                        (op->dvr_kernel == 2 || (op->dvr_kernel == 0 && op->D >= kDvrMfmaMinD));
+    const bool tbf16 = toeplitz && nv == 1 && op->dvr_kernel == 3;
     const int variant = toeplitz ? dvr_toeplitz_variant((int32_t)op->D, nv) : 0;
     const int chunk = toeplitz ? dvr_toeplitz_chunk_of(variant) : 1;
-    out.n_slots = tmfma ? dvr_mfma_chunks((int32_t)op->D)
+    out.n_slots = tbf16 ? dvr_bf16_chunks((int32_t)op->D)
+                : tmfma ? dvr_mfma_chunks((int32_t)op->D)
                 : toeplitz ? (int32_t)((op->D + chunk - 1) / chunk) : op->n_super + 1;
     out.vdiag = (toeplitz && !op->comp()) ? op->d_v : nullptr;
     out.nv_stride = nv;
@@ -430,7 +433,9 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
         a.ldx = ldx;
         a.P = out.P;
         a.ldp = (int64_t)ldp;
-        if (tmfma)
+        if (tbf16)
+            HIP_TRY(launch_dvr_toeplitz_bf16(a, s, timed ? e0 : nullptr, e1));
+        else if (tmfma)
             HIP_TRY(launch_dvr_toeplitz_mfma(a, s, timed ? e0 : nullptr, e1));
         else
             HIP_TRY(launch_dvr_toeplitz(a, nv, variant, s, timed ? e0 : nullptr, e1));
@@ -1789,7 +1794,7 @@ procmv_status procmv_set_dvr_kernel(procmv_op_t H, int32_t kind)
 {
     procmv_status st = check_op(H);
     if (st != PROCMV_OK) return st;
-    if (kind < 0 || kind > 2) return fail(PROCMV_ERR_INVALID_ARG, "kernel kind %d", kind);
+    if (kind < 0 || kind > 3) return fail(PROCMV_ERR_INVALID_ARG, "kernel kind %d", kind);
     H->dvr_kernel = kind;
     return PROCMV_OK;
 }

@@ -248,6 +248,12 @@ constexpr int32_t kDvrMfmaMinD = 16384;   // default routing: from this D on
 int dvr_mfma_chunks(int32_t D);
 hipError_t launch_dvr_toeplitz_mfma(const DvrToeplitzArgs& a, hipStream_t s,
                                     hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// The same product on the bfloat16 matrix cores with an exact three-piece
+// split of the binary32 operands (defined in dvr_bf16.hip): partial slots =
+// dvr_bf16_chunks(D), layout as above.
+int dvr_bf16_chunks(int32_t D);
+hipError_t launch_dvr_toeplitz_bf16(const DvrToeplitzArgs& a, hipStream_t s,
+                                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Batched reduction and completion (defined in batch.hip).
 hipError_t launch_reduce_batched(const BatchReduceArgs& a, Epi mode, hipStream_t s);
 hipError_t launch_finish_batched(const BatchReduceItem* items, int n, int nv,

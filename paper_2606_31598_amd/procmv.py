@@ -535,7 +535,8 @@ class Operator:
 
     def set_dvr_kernel(self, kind):
         """Procedural sinc-DVR product kernel: 0 automatic, 1 VALU Toeplitz
-        kernel, 2 matrix-core Toeplitz kernel (one vector per launch)."""
+        kernel, 2 binary32 matrix-core Toeplitz kernel, 3 split-bf16
+        matrix-core Toeplitz kernel (2 and 3: one vector per launch)."""
         _check(load().procmv_set_dvr_kernel(self._h, int(kind)))
         return self
 

@@ -1,10 +1,13 @@
-"""GPU parity of the matrix-core sinc-DVR Toeplitz kernel (one vector)
+"""GPU parity of the matrix-core sinc-DVR Toeplitz kernels (one vector)
 against the binary64 oracle and against the VALU Toeplitz kernel.
 
-The kernel cuts the operator into 32 x 32 Toeplitz blocks T_d (one per block
-offset d) and applies each to all output blocks at once on the matrix cores;
-ragged D, operators smaller than one block and both arithmetics (plain and
-compensated, whose tables drop the band |i - j| < 32) are covered.
+Both kernels cut the operator into 32 x 32 Toeplitz blocks T_d (one per block
+offset d) and apply each to all output blocks at once on the matrix cores:
+kind 2 in binary32 MFMA, kind 3 on the bfloat16 matrix cores with an exact
+three-piece split of every binary32 operand (six piece products, binary32
+accumulation).  Ragged D, operators smaller than one block and both
+arithmetics (plain and compensated, whose tables drop the band |i - j| < 32)
+are covered, with the tolerances of binary32 products.
 """
 import numpy as np
 import pytest
@@ -26,8 +29,9 @@ def pm():
     return procmv
 
 
+@pytest.mark.parametrize("kind", [2, 3])
 @pytest.mark.parametrize("D", [2, 33, 100, 1000, 2047, 5000, 16384, 20000])
-def test_mfma_toeplitz_matches_oracle(pm, orc, D):
+def test_mfma_toeplitz_matches_oracle(pm, orc, D, kind):
     d = orc.DVR(D)
     # inputs rounded to complex64 first: the oracle applies the operator to
     # exactly the vector the GPU reads (for the smooth vector the rounding
@@ -35,9 +39,9 @@ def test_mfma_toeplitz_matches_oracle(pm, orc, D):
     X = workloads.gaussian_vectors(D, 1, seed=D).astype(np.complex64)
     S = workloads.wavepacket(D).astype(np.complex64)
     for prec in (pm.FP32, pm.FP32_COMPENSATED):
-        op = pm.Operator.dvr(D).plan(256, precision=prec).set_dvr_kernel(2)
+        op = pm.Operator.dvr(D).plan(256, precision=prec).set_dvr_kernel(kind)
         err = rel_l2(to_host(op.apply(to_dev(X))), d.apply_rows(X))
-        print(f"D={D} precision={prec} random {err:.2e}")
+        print(f"D={D} kind={kind} precision={prec} random {err:.2e}")
         assert err < 1e-5
         if prec == pm.FP32_COMPENSATED:
             # smooth vector: error of the rescaled operator (H - c)/R, the
@@ -47,35 +51,53 @@ def test_mfma_toeplitz_matches_oracle(pm, orc, D):
             got_s = to_host(op.apply(to_dev(S)))
             sc = float(np.linalg.norm(got_s - ref_s) / (R * np.linalg.norm(S)))
             err_s = rel_l2(got_s, ref_s)
-            print(f"D={D} compensated smooth rel {err_s:.2e} scaled {sc:.1e}")
+            print(f"D={D} kind={kind} compensated smooth rel {err_s:.2e} scaled {sc:.1e}")
             assert err_s < 1e-5 or sc < 1e-9
         op.close()
 
 
-def test_mfma_and_valu_toeplitz_agree(pm):
-    """Same entries, different summation order: the two kernels' products
-    agree to binary32 rounding."""
+@pytest.mark.parametrize("kind", [2, 3])
+def test_mfma_and_valu_toeplitz_agree(pm, kind):
+    """Same entries, different summation order (and, for kind 3, the
+    split's dropped products): the products agree to binary32 rounding."""
     D = 20000
     X = to_dev(workloads.gaussian_vectors(D, 1, seed=3))
     op = pm.Operator.dvr(D).plan(256)
     a = to_host(op.set_dvr_kernel(1).apply(X))
-    b = to_host(op.set_dvr_kernel(2).apply(X))
+    b = to_host(op.set_dvr_kernel(kind).apply(X))
     assert rel_l2(b, a) < 2e-6
 
 
-def test_mfma_propagation_matches_oracle(pm, orc):
-    """Compensated propagation with the matrix-core product at D = 4096,
+def test_split_kernel_is_deterministic_and_row_exact_on_integers(pm, orc):
+    """Small integers are exact in every piece and product: with a vector of
+    integers in [-8, 8] the split products reproduce the binary64 row sums of
+    the binary32 entries to a few binary32 roundings of the partial sums, and
+    two launches give the same bits."""
+    D = 3000
+    d = orc.DVR(D)
+    rng = np.random.default_rng(11)
+    X = (rng.integers(-8, 9, D) + 1j * rng.integers(-8, 9, D)).astype(np.complex64)[None, :]
+    op = pm.Operator.dvr(D).plan(256).set_dvr_kernel(3)
+    a = to_host(op.apply(to_dev(X)))
+    b = to_host(op.apply(to_dev(X)))
+    assert np.array_equal(a, b)
+    assert rel_l2(a, d.apply_rows(X)) < 1e-6
+
+
+@pytest.mark.parametrize("kind", [2, 3])
+def test_mfma_propagation_matches_oracle(pm, orc, kind):
+    """Compensated propagation with a matrix-core product at D = 4096,
     20 steps, against the binary64 oracle and the scaled budget."""
     D, dt, steps = 4096, 0.05, 20
     d = orc.DVR(D)
     e0, e1 = d.spectral_bounds()
     c, R = 0.5 * (e0 + e1), 0.5 * (e1 - e0)
-    op = pm.Operator.dvr(D).plan(256, precision=pm.FP32_COMPENSATED).set_dvr_kernel(2)
+    op = pm.Operator.dvr(D).plan(256, precision=pm.FP32_COMPENSATED).set_dvr_kernel(kind)
     psi0 = workloads.wavepacket(D).astype(np.complex64)
     P = to_dev(psi0)
     op.propagate(P, dt, nsteps=steps, c=c, R=R)
     ref = ch.propagate(lambda v: d.apply_fft(v), psi0, c, R, dt, ch.cheb_order(R * dt),
                        nsteps=steps)
     err = rel_l2(to_host(P), ref)
-    print(f"D={D} steps={steps} vs fp64 {err:.2e}")
+    print(f"D={D} kind={kind} steps={steps} vs fp64 {err:.2e}")
     assert err < 1e-4 * np.sqrt(steps / 200.0)
