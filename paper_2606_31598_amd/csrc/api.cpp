@@ -399,9 +399,9 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
     const bool mfma = use_mfma(op, nv);
     const bool toeplitz = !mfma && op->gen == 1 && op->p_cache == 0;
     // one vector of a large operator: the Toeplitz blocks on the matrix cores
-    const bool tmfma = toeplitz && nv == 1 &&
-                       (op->dvr_kernel == 2 || (op->dvr_kernel == 0 && op->D >= kDvrMfmaMinD));
-    const bool tbf16 = toeplitz && nv == 1 && op->dvr_kernel == 3;
+    const bool tmfma = toeplitz && nv == 1 && op->dvr_kernel == 2;
+    const bool tbf16 = toeplitz && nv == 1 &&
+                       (op->dvr_kernel == 3 || (op->dvr_kernel == 0 && op->D >= kDvrMfmaMinD));
     const int variant = toeplitz ? dvr_toeplitz_variant((int32_t)op->D, nv) : 0;
     const int chunk = toeplitz ? dvr_toeplitz_chunk_of(variant) : 1;
     out.n_slots = tbf16 ? dvr_bf16_chunks((int32_t)op->D)

@@ -69,12 +69,20 @@ __device__ __forceinline__ uint32_t top16(float v)
     return __float_as_uint(v) >> 16;
 }
 
-// v = hi + mid + lo exactly (normal v): truncation to the top 16 bits twice.
+// v rounded to the nearest bfloat16 (ties to even), as a binary32 value.
+__device__ __forceinline__ float round_bf16(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    return __uint_as_float((u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u);
+}
+
+// v = hi + mid + lo exactly (normal v): |v - hi| <= 2^-9 |v| has at most 16
+// significant bits, |v - hi - mid| at most 8, so lo is a bfloat16 as it is.
 __device__ __forceinline__ void split3(float v, uint32_t& h, uint32_t& m, uint32_t& l)
 {
-    const float vh = __uint_as_float(__float_as_uint(v) & 0xFFFF0000u);
+    const float vh = round_bf16(v);
     const float r1 = v - vh;
-    const float vm = __uint_as_float(__float_as_uint(r1) & 0xFFFF0000u);
+    const float vm = round_bf16(r1);
     const float r2 = r1 - vm;
     h = top16(vh);
     m = top16(vm);
@@ -205,21 +213,27 @@ __global__ __launch_bounds__(kThreads) void dvr_toeplitz_bf16x6_kernel(DvrToepli
             B1[P] = *(const uint4*)&xs[P][row1][16 * h + 8 * kg];
         }
     };
-    f32x16 acc0 = {}, acc1 = {};
-    // hh, hm, mh, hl, lh, mm; the two tiles alternate
+    // hh products and the five smaller ones in separate accumulators: added
+    // to a sum of hh products, most of a smaller product falls below half a
+    // unit of its last place and is rounded away, and what is lost is part of
+    // t x with the sign of t x, not noise (a shift of the operator's energy,
+    // about -8e-5 at D = 32768 for a smooth vector); in their own sum they keep
+    // their digits, and the two sums meet once after the loop
+    f32x16 acc0 = {}, acc1 = {}, low0 = {}, low1 = {};
+    // hh | hm, mh, hl, lh, mm; the two tiles alternate
     auto products = [&](const uint4 (&A)[3], const uint4 (&B0)[3], const uint4 (&B1)[3]) {
         acc0 = mfma(A[0], B0[0], acc0);
         acc1 = mfma(A[0], B1[0], acc1);
-        acc0 = mfma(A[0], B0[1], acc0);
-        acc1 = mfma(A[0], B1[1], acc1);
-        acc0 = mfma(A[1], B0[0], acc0);
-        acc1 = mfma(A[1], B1[0], acc1);
-        acc0 = mfma(A[0], B0[2], acc0);
-        acc1 = mfma(A[0], B1[2], acc1);
-        acc0 = mfma(A[2], B0[0], acc0);
-        acc1 = mfma(A[2], B1[0], acc1);
-        acc0 = mfma(A[1], B0[1], acc0);
-        acc1 = mfma(A[1], B1[1], acc1);
+        low0 = mfma(A[0], B0[1], low0);
+        low1 = mfma(A[0], B1[1], low1);
+        low0 = mfma(A[1], B0[0], low0);
+        low1 = mfma(A[1], B1[0], low1);
+        low0 = mfma(A[0], B0[2], low0);
+        low1 = mfma(A[0], B1[2], low1);
+        low0 = mfma(A[2], B0[0], low0);
+        low1 = mfma(A[2], B1[0], low1);
+        low0 = mfma(A[1], B0[1], low0);
+        low1 = mfma(A[1], B1[1], low1);
     };
     // this wave's offsets: d0 + dp, d0 + dp + 2, ...; software pipeline: the
     // fragments of the next step are read while the matrix cores work on the
@@ -237,6 +251,12 @@ __global__ __launch_bounds__(kThreads) void dvr_toeplitz_bf16x6_kernel(DvrToepli
         __builtin_amdgcn_sched_group_barrier(0x008, 12, 0);   // MFMAs
         __builtin_amdgcn_sched_group_barrier(0x100, 12, 0);
         __builtin_amdgcn_sched_group_barrier(0x008, 12, 0);
+    }
+
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        acc0[r] += low0[r];
+        acc1[r] += low1[r];
     }
 
     // Sums of the two waves of a tile pair, then coalesced stores: the
