@@ -19,12 +19,15 @@
 // block and 16 columns of K that is six bf16 MFMAs of 32 cycles against eight
 // binary32 32x32x2 MFMAs of 64 cycles: 2.7x fewer matrix-core cycles.
 //
-// Layout: a workgroup of 8 waves owns 128 consecutive output blocks and one
+// Layout: a workgroup of 8 waves owns 64 consecutive output blocks and one
 // chunk of block offsets d; each wave owns two column tiles of 16 blocks
 // (32 MFMA columns: 16 blocks x {re, im}), so every A fragment it reads
-// feeds two MFMAs, and shares them with a second wave that takes the other
-// parity of d (two waves per SIMD hide each other's LDS latency; their sums
-// meet in LDS, and the workgroup's rows leave in coalesced 16-byte stores).  The x window (3 pieces) sits in LDS with a row per
+// feeds two MFMAs, and shares them with three more waves that take the other
+// phases of d mod 4 (two waves per SIMD hide each other's LDS latency; their
+// sums meet in LDS, and the workgroup's rows leave in coalesced 16-byte
+// stores).  64 blocks per workgroup keep the chunks long (16 partial slots at
+// D = 32768): the slots are written, flushed at the end of the kernel and read
+// again by the reduction, and fewer of them shorten all three.  The x window (3 pieces) sits in LDS with a row per
 // (block, component) and an 80-byte row pitch, so the 16-byte B reads of 16
 // lanes hit 16 distinct groups of 4 banks.  A lane's A fragment is 8
 // consecutive symbol values starting at an offset that varies with its row p;
@@ -48,16 +51,17 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kBlk = 32;            // Toeplitz block edge
 constexpr int kTileBlocks = 16;     // output blocks per MFMA column tile
 constexpr int kWaveTiles = 2;       // column tiles per wave
-constexpr int kTileGroups = 4;      // pairs of column tiles per workgroup
-constexpr int kThreads = 512;       // 8 waves: 2 per tile pair (even / odd offsets)
-constexpr int kGroupBlocks = kTileBlocks * kWaveTiles * kTileGroups;   // 128
+constexpr int kTileGroups = 2;      // pairs of column tiles per workgroup
+constexpr int kPhases = 4;          // waves per tile pair, each taking every 4th offset
+constexpr int kThreads = 64 * kTileGroups * kPhases;   // 8 waves
+constexpr int kGroupBlocks = kTileBlocks * kWaveTiles * kTileGroups;   // 64
 constexpr int kOutPitch = 68;       // floats per output block in the LDS transpose
-constexpr int kMaxChunk = 40;       // block offsets per workgroup (LDS sizing)
+constexpr int kMaxChunk = 72;       // block offsets per workgroup (LDS sizing)
 constexpr int kTargetGroups = 256;  // about one workgroup per compute unit
 constexpr int kXBlocks = kGroupBlocks + kMaxChunk - 1;
 constexpr int kXRow = 40;           // bf16 per (block, component) row: 32 + 8 pad
 // symbol window: 32 L + 31 entries for a chunk of L offsets; each shifted
-// copy padded to 1360 entries (680 dwords = 8 mod 32: the four copies start
+// copy padded to 16 mod 64 entries (8 mod 32 dwords: the four copies start
 // 8 banks apart, so the 8-byte reads of 16 lanes, 4 rows x 4 copies, cover
 // the 32 banks once)
 constexpr int kSymLen = kBlk * kMaxChunk + kBlk - 1;
@@ -182,8 +186,8 @@ __global__ __launch_bounds__(kThreads) void dvr_toeplitz_bf16x6_kernel(DvrToepli
 
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int tg = w & (kTileGroups - 1);   // tile pair of this wave
-    const int dp = w / kTileGroups;         // parity of its block offsets
+    const int tg = w % kTileGroups;   // tile pair of this wave
+    const int dp = w / kTileGroups;   // phase of its block offsets
     const int p = lane & 31;             // A row; also the B / C column n
     const int kg = lane >> 5;            // K group: k = 8 kg + j
     const int nb = p >> 1;               // output block within a column tile
@@ -235,15 +239,15 @@ __global__ __launch_bounds__(kThreads) void dvr_toeplitz_bf16x6_kernel(DvrToepli
         low0 = mfma(A[1], B0[1], low0);
         low1 = mfma(A[1], B1[1], low1);
     };
-    // this wave's offsets: d0 + dp, d0 + dp + 2, ...; software pipeline: the
+    // this wave's offsets: d0 + dp, d0 + dp + 4, ...; software pipeline: the
     // fragments of the next step are read while the matrix cores work on the
     // current one (the last pass re-reads a valid step and discards it)
     uint4 A0[3], B00[3], B10[3], A1[3], B01[3], B11[3];
     if (d0 + dp < d1) load_step(d0 + dp, 0, A0, B00, B10);
-    for (int d = d0 + dp; d < d1; d += 2) {
+    for (int d = d0 + dp; d < d1; d += kPhases) {
         load_step(d, 1, A1, B01, B11);
         products(A0, B00, B10);
-        load_step(d + 2 < d1 ? d + 2 : d, 0, A0, B00, B10);
+        load_step(d + kPhases < d1 ? d + kPhases : d, 0, A0, B00, B10);
         products(A1, B01, B11);
         // schedule as written: the 12 LDS reads of the next step issue ahead
         // of the 12 MFMAs of the current one, so they run under them
@@ -259,30 +263,30 @@ __global__ __launch_bounds__(kThreads) void dvr_toeplitz_bf16x6_kernel(DvrToepli
         acc1[r] += low1[r];
     }
 
-    // Sums of the two waves of a tile pair, then coalesced stores: the
-    // workgroup's 128 x 32 rows go through LDS (the staging arrays are free
-    // once every wave has left the loop), ob[block * kOutPitch + 2 row + c].
+    // Sums of the four waves of a tile pair, then coalesced stores: the
+    // workgroup's 64 x 32 rows go through LDS (the staging arrays are free
+    // once every wave has left the loop), ob[block * kOutPitch + 2 row + c],
+    // the phases adding in a fixed order.
     // C[row][n]: lane holds column n, rows 8 (r >> 2) + 4 kg + (r & 3).
     float* ob = reinterpret_cast<float*>(&xs[0][0][0]);
     static_assert(kGroupBlocks * kOutPitch * sizeof(float) <= sizeof(xs), "output staging");
     const int ob0 = (kWaveTiles * kTileBlocks * tg + nb) * kOutPitch + comp;
     const int ob1 = ob0 + kTileBlocks * kOutPitch;
-    __syncthreads();
-    if (dp == 1) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int ro = 8 * (r >> 2) + 4 * kg + (r & 3);
-            ob[ob0 + 2 * ro] = acc0[r];
-            ob[ob1 + 2 * ro] = acc1[r];
-        }
-    }
-    __syncthreads();
-    if (dp == 0) {
+    for (int ph = kPhases - 1; ph >= 0; --ph) {
+        __syncthreads();
+        if (dp == ph) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int ro = 8 * (r >> 2) + 4 * kg + (r & 3);
-            ob[ob0 + 2 * ro] += acc0[r];
-            ob[ob1 + 2 * ro] += acc1[r];
+            for (int r = 0; r < 16; ++r) {
+                const int ro = 8 * (r >> 2) + 4 * kg + (r & 3);
+                if (ph == kPhases - 1) {
+                    ob[ob0 + 2 * ro] = acc0[r];
+                    ob[ob1 + 2 * ro] = acc1[r];
+                } else {
+                    ob[ob0 + 2 * ro] += acc0[r];
+                    ob[ob1 + 2 * ro] += acc1[r];
+                }
+            }
         }
     }
     __syncthreads();
