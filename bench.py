@@ -4,9 +4,10 @@ Default workload: sinc-DVR harmonic oscillator, D = 32768 on x in [-20, 20],
 wavepacket at x0 = 3 (sigma = 1), Chebyshev propagation with dt = 0.05 and
 the order from the Bessel-coefficient rule.  One benchmark step is one
 Chebyshev time step: K + 1 coefficient terms, K products H q (each one
-generated-block product over all D^2 entries, by default the matrix-core
-Toeplitz kernel, plus its fixed-order reduction with the recurrence and the
-binary64 accumulation fused), and the final rounding and binary64 norm.  The
+generated-block product over all D^2 entries, by default the split-bf16
+matrix-core Toeplitz kernel, plus its fixed-order reduction with the
+recurrence and the binary64 accumulation fused), and the final rounding and
+binary64 norm.  The
 default arithmetic is the compensated binary32 one (band in difference form,
 hi + lo recurrence vectors), which keeps the state within 1e-4 sqrt(n/200)
 of the exact one; --precision fp32 gives the plain binary32 arithmetic.
@@ -33,7 +34,12 @@ if ROOT not in sys.path:
 METRIC = ("Gelem/s of H applied (procedural vs cached) & Chebyshev steps/s "
           "at stated err")
 PEAK_FP32_TFLOPS = 157.3   # MI355X fp32: vector and dense matrix cores (published)
+PEAK_BF16_TFLOPS = 2500.0  # MI355X bf16 dense matrix cores (published)
 PEAK_HBM_GBS = 8000.0
+# the split-bf16 product applies six bfloat16 piece products per entry and
+# vector component (hh, hm, mh, hl, lh, mm) where a binary32 product applies one
+SPLIT_PRODUCTS = 6
+KINDS = {"auto": 0, "valu": 1, "mfma": 2, "split": 3}
 
 
 def log(msg):
@@ -42,10 +48,21 @@ def log(msg):
 
 CSRC = os.path.join(ROOT, "paper_2606_31598_amd", "csrc")
 # dominant kernel per --dvr-kernel: (counter summary, kernel source)
-PMC = {"mfma": (os.path.join(ROOT, "profiles", "dvr_toeplitz_mfma_D32768_pmc.txt"),
+PMC = {"split": (os.path.join(ROOT, "profiles", "dvr_toeplitz_bf16x6_D32768_pmc.txt"),
+                 os.path.join(CSRC, "dvr_bf16.hip")),
+       "mfma": (os.path.join(ROOT, "profiles", "dvr_toeplitz_mfma_D32768_pmc.txt"),
                 os.path.join(CSRC, "dvr_mfma.hip")),
        "valu": (os.path.join(ROOT, "profiles", "dvr_toeplitz_D32768_pmc.txt"),
                 os.path.join(CSRC, "dvr.hip"))}
+KERNEL_NAMES = {"split": "dvr_toeplitz_bf16x6_kernel", "mfma": "dvr_toeplitz_mfma_kernel",
+                "valu": "dvr_toeplitz_kernel"}
+
+
+def resolve_kernel(choice, D):
+    """Kernel the library runs for one vector of the procedural operator."""
+    if choice == "auto":
+        return "split" if D >= 16384 else "valu"
+    return choice
 
 
 def counted_traffic(kernel):
@@ -151,7 +168,7 @@ def run_dvr(args):
     frac = {"procedural": 0.0, "partial": 0.5, "full": 1.0}[args.strategy]
     prec = {"fp32": pm.FP32, "compensated": pm.FP32_COMPENSATED}[args.precision]
     log(f"DVR D={D} b={b} strategy={args.strategy} precision={args.precision}")
-    kind = {"auto": 0, "valu": 1, "mfma": 2}[args.dvr_kernel]
+    kind = KINDS[args.dvr_kernel]
     op = pm.Operator.dvr(D).plan(b, strat, frac, precision=prec).set_dvr_kernel(kind)
     c, R = op.spectral_bounds()
     K = pm.cheb_order(R * dt, 1e-10)
@@ -188,13 +205,23 @@ def run_dvr(args):
     tile_avg = prof["tile_ms"] / max(prof["tile_n"], 1) / 1e3
     red_avg = prof["reduce_ms"] / max(prof["reduce_n"], 1) / 1e3
     flops = 4.0 * D * D      # real entry x complex vector: 2 FMA per element
-    achieved = flops / tile_avg / 1e12
-    mfma = args.dvr_kernel == "mfma" or (args.dvr_kernel == "auto" and D >= 16384)
+    kern = resolve_kernel(args.dvr_kernel, D)
+    if kern == "split":
+        # algorithmic work of the split-bf16 product: six piece products
+        roof = {"bound": "mfma", "achieved": SPLIT_PRODUCTS * flops / tile_avg / 1e12,
+                "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "mfma" if kern == "mfma" else "alu",
+                "achieved": flops / tile_avg / 1e12, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = counted_traffic(kern)
     out = {
         "metric": METRIC, "value": value, "unit": "Gelem/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x3 split of f32 (f32 accumulate)" if kern == "split" else "f32",
         "data": "synthetic",
         "config": {"workload": f"sinc-DVR harmonic oscillator D={D}, x in [-20,20], "
                                f"wavepacket x0=3 sigma=1, Chebyshev dt={dt}, "
@@ -208,11 +235,12 @@ def run_dvr(args):
         "reduce_kernel_avg_us": red_avg * 1e6,
         "timed_launches": {"tile": prof["tile_n"], "reduce": prof["reduce_n"],
                            "sampled_every": args.profile_every},
-        "dominant_kernel": "dvr_toeplitz_mfma_kernel" if mfma else "dvr_toeplitz_kernel",
-        "roofline": {"bound": "mfma" if mfma else "alu", "achieved": achieved,
-                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": counted_traffic("mfma" if mfma else "valu")},
+        "dominant_kernel": KERNEL_NAMES[kern],
+        "roofline": roof,
+        # binary32-equivalent rate of the product (4 D^2 flop) against the
+        # binary32 peak, for comparison with the binary32 kernels
+        "fp32_equivalent": {"achieved": flops / tile_avg / 1e12, "peak": PEAK_FP32_TFLOPS,
+                            "unit": "TFLOP/s", "frac": flops / tile_avg / 1e12 / PEAK_FP32_TFLOPS},
     }
 
     if args.modes:
@@ -258,7 +286,7 @@ def pmc_probe(args):
     from paper_2606_31598_amd import workloads
     D = args.D
     prec = {"fp32": pm.FP32, "compensated": pm.FP32_COMPENSATED}[args.precision]
-    kind = {"auto": 0, "valu": 1, "mfma": 2}[args.dvr_kernel]
+    kind = KINDS[args.dvr_kernel]
     op = pm.Operator.dvr(D).plan(args.block, precision=prec).set_dvr_kernel(kind)
     X = torch.from_numpy(workloads.gaussian_vectors(D, 1, seed=2).astype(np.complex64)).cuda()
     Y = torch.empty_like(X)
@@ -283,8 +311,10 @@ def main():
                     choices=["procedural", "partial", "full"])
     ap.add_argument("--precision", default="compensated", choices=["fp32", "compensated"],
                     help="binary32 arithmetic of the products and the recurrence")
-    ap.add_argument("--dvr-kernel", default="mfma", choices=["auto", "valu", "mfma"],
-                    help="procedural sinc-DVR product: matrix-core or VALU Toeplitz kernel")
+    ap.add_argument("--dvr-kernel", default="auto", choices=list(KINDS),
+                    help="procedural sinc-DVR product: split = bf16 matrix cores with an "
+                         "exact three-piece split, mfma = binary32 matrix cores, valu = "
+                         "binary32 FMA; auto = the library's choice (split from D = 16384)")
     ap.add_argument("--profile-every", type=int, default=16)
     ap.add_argument("--mode-reps", type=int, default=50)
     ap.add_argument("--no-modes", dest="modes", action="store_false")
