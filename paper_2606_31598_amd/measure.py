@@ -14,6 +14,9 @@ configuration; accuracy against the binary64 reference lives in the tests.
 * c3 -- Philox-GUE D = 262144, 16 vectors, b = 512: procedural and 25%
   canonical cache, binary32 and split-bfloat16 matrix-core products; cache
   fill time and the bandwidth of the cached part.
+* probe -- a few products of each configuration above (C0: 20; C2: 3 batched;
+  C3: 2 per arithmetic and storage mode), for hardware-counter and
+  kernel-trace runs.
 * modes -- single-vector products of one operator (Philox-GUE or sinc-DVR,
   D = 32768 by default, b = 256) in each storage mode: procedural, 50%
   canonical cache, full cache; cache bytes and the rate they are read at.
@@ -149,6 +152,49 @@ def c3(reps):
             torch.cuda.synchronize()
 
 
+def probe():
+    torch = _cuda()
+    from . import procmv as pm, workloads
+    # C0
+    D = 2048
+    op = pm.Operator.gue(D, seed=1).plan(256, pm.PROCEDURAL)
+    X = torch.from_numpy(workloads.gaussian_vectors(D, 1, seed=2).astype(np.complex64)).cuda()
+    Y = torch.empty_like(X)
+    for _ in range(20):
+        op.apply(X, Y)
+    torch.cuda.synchronize()
+    op.close()
+    _emit({"probe": "c0", "products": 20})
+    # C2: the default batch configuration (no autotuning)
+    sizes = workloads.batch_sizes(256)
+    nvec = 4
+    ops = [pm.Operator.gue(int(Dk), seed=k + 1).plan(256) for k, Dk in enumerate(sizes)]
+    B = pm.Batch(ops, nvec)
+    parts = [workloads.gaussian_vectors(int(Dk), nvec, seed=100 + k).ravel()
+             for k, Dk in enumerate(sizes)]
+    X = torch.from_numpy(np.concatenate(parts).astype(np.complex64)).cuda()
+    Y = torch.empty_like(X)
+    for _ in range(3):
+        B.apply(X, Y)
+    torch.cuda.synchronize()
+    _emit({"probe": "c2", "products": 3, "batch_config": B.info()})
+    del B, ops
+    # C3
+    D, nvec, b = 262144, 16, 512
+    X = torch.from_numpy(workloads.gaussian_vectors(D, nvec, seed=2).astype(np.complex64)).cuda()
+    Y = torch.empty_like(X)
+    for strat, f in ((pm.PROCEDURAL, 0.0), (pm.PARTIAL, 0.25)):
+        for prec, pname in ((pm.FP32, "fp32"), (pm.SPLIT_BF16, "split_bf16")):
+            op = pm.Operator.gue(D, seed=1).plan(b, strat, f, precision=prec)
+            for _ in range(2):
+                op.apply(X, Y)
+            torch.cuda.synchronize()
+            op.close()
+            torch.cuda.synchronize()
+            _emit({"probe": "c3", "strategy": "procedural" if f == 0 else f"partial {f}",
+                   "precision": pname, "products": 2})
+
+
 def modes(reps, family="gue", D=32768):
     torch = _cuda()
     from . import procmv as pm, workloads
@@ -248,7 +294,7 @@ def kron(reps):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["c0", "c2", "c3", "modes", "lanczos", "filter", "kron"])
+    ap.add_argument("cmd", choices=["c0", "c2", "c3", "probe", "modes", "lanczos", "filter", "kron"])
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--family", choices=["gue", "dvr"], default="gue")
     ap.add_argument("--D", type=int, default=32768)
@@ -261,6 +307,8 @@ def main(argv=None):
         filt(args.reps)
     elif args.cmd == "kron":
         kron(args.reps)
+    elif args.cmd == "probe":
+        probe()
     else:
         {"c0": c0, "c2": c2, "c3": c3}[args.cmd](args.reps)
 
