@@ -32,9 +32,12 @@ def _apply_noalloc(pm, op, X, Y):
 def test_noalloc_matches_apply_on_two_calls(pm):
     import torch
     cases = [
-        # GUE, 4 vectors, half-cached: 64-wide-edge super-tiles of a ragged D
+        # one vector of the compensated sinc-DVR operator at D = 20000: the
+        # split-bf16 matrix-core product (26 partial slots)
+        (pm.Operator.dvr(20000).plan(256, precision=pm.FP32_COMPENSATED), 1, 13),
+        # smaller: GUE, 4 vectors, half-cached: 64-wide-edge super-tiles of a ragged D
         (pm.Operator.gue(3000, seed=7).plan(256, pm.PARTIAL, 0.5), 4, 11),
-        # smaller: one vector of the compensated sinc-DVR operator
+        # smaller still: one vector of the compensated sinc-DVR operator (VALU)
         (pm.Operator.dvr(1500).plan(128, precision=pm.FP32_COMPENSATED), 1, 12),
     ]
     for op, nv, seed in cases:
