@@ -7,17 +7,19 @@
 // Toeplitz block per block offset d, shared by every output block I.
 //
 // Every binary32 value v (symbol entry or vector component) is written as
-// v = hi + mid + lo with three bfloat16 pieces taken by truncation: hi keeps
-// the top 8 significand bits of v, mid the next 8 of the remainder, lo the
-// rest, and each subtraction is exact.  Products of pieces are exact in
-// binary32, so the six products whose piece levels sum to at most two
+// v = hi + mid + lo with three bfloat16 pieces: hi = v rounded to the nearest
+// bfloat16, mid = the remainder rounded likewise, lo = what is left (at most
+// 8 significant bits), each subtraction exact.  Products of pieces are exact
+// in binary32, so the six products whose piece levels sum to at most two
 // (hh, hm, mh, hl, lh, mm) reproduce t x up to the dropped mid-lo, lo-mid and
-// lo-lo terms, at most about 2^-23 |t x|: the rounding level of a binary32
-// product.  They run as v_mfma_f32_32x32x16_bf16 with binary32 accumulation
-// (the split-BF16 application of the paper's precision options, with a third
-// piece so that nothing coarser than binary32 rounding enters).  Per 32 x 32
-// block and 16 columns of K that is six bf16 MFMAs of 32 cycles against eight
-// binary32 32x32x2 MFMAs of 64 cycles: 2.7x fewer matrix-core cycles.
+// lo-lo terms, below 2^-25 |t x| and of either sign: the rounding level of a
+// binary32 product.  They run as v_mfma_f32_32x32x16_bf16 with binary32
+// accumulation (the split-BF16 application of the paper's precision options,
+// with a third piece so that nothing coarser than binary32 rounding enters),
+// the hh products and the five smaller ones in separate sums (see the
+// accumulators below).  Per 32 x 32 block and 16 columns of K that is six
+// bf16 MFMAs of 32 cycles against eight binary32 32x32x2 MFMAs of 64 cycles:
+// 2.7x fewer matrix-core cycles.
 //
 // Layout: a workgroup of 8 waves owns 64 consecutive output blocks and one
 // chunk of block offsets d; each wave owns two column tiles of 16 blocks
@@ -26,17 +28,17 @@
 // phases of d mod 4 (two waves per SIMD hide each other's LDS latency; their
 // sums meet in LDS, and the workgroup's rows leave in coalesced 16-byte
 // stores).  64 blocks per workgroup keep the chunks long (16 partial slots at
-// D = 32768): the slots are written, flushed at the end of the kernel and read
-// again by the reduction, and fewer of them shorten all three.  The x window (3 pieces) sits in LDS with a row per
-// (block, component) and an 80-byte row pitch, so the 16-byte B reads of 16
-// lanes hit 16 distinct groups of 4 banks.  A lane's A fragment is 8
-// consecutive symbol values starting at an offset that varies with its row p;
-// the symbol window is kept in four copies shifted by 0..3 entries, and lane p
-// reads the copy in which its run starts on an 8-byte boundary (two
-// ds_read_b64, kept apart).  Each chunk's sums go to one partial slot,
-// reduced in a fixed order afterwards.  The symbol comes from the same binary32 table as the
-// other Toeplitz kernels (zero at k = 0 and, for the compensated arithmetic,
-// inside the band).
+// D = 32768): the slots are written, flushed at the end of the kernel and
+// read again by the reduction, and fewer of them shorten all three.  The x
+// window (3 pieces) sits in LDS with a row per (block, component) and an
+// 80-byte row pitch, so the 16-byte B reads of 16 lanes hit 16 distinct
+// groups of 4 banks.  A lane's A fragment is 8 consecutive symbol values
+// starting at an offset that varies with its row p; the symbol window is kept
+// in four copies shifted by 0..3 entries, and lane p reads the copy in which
+// its run starts on an 8-byte boundary (two ds_read_b64, kept apart).  Each
+// chunk's sums go to one partial slot, reduced in a fixed order afterwards.
+// The symbol comes from the same binary32 table as the other Toeplitz kernels
+// (zero at k = 0 and, for the compensated arithmetic, inside the band).
 #include <hip/hip_ext.h>
 
 #include "kernels.h"
