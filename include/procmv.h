@@ -341,7 +341,8 @@ procmv_status procmv_set_tile_shape(procmv_op_t H, int32_t shape);
  * down to the binary32 rounding level (hh, hm, mh, hl, lh, mm) are
  * accumulated in binary32 by MFMA 32x32x16, the hh products and the smaller
  * ones in separate sums (split-BF16 application with a third piece; the
- * dropped products are below 2^-25 of each entry's product), kind 0 =
+ * dropped products are at most 2^-23 of each entry's product, about 2^-27
+ * in root mean square, and of either sign), kind 0 =
  * automatic (kind 3 for one vector from D = 16384 on, VALU otherwise).
  * Launches of several vectors always take the VALU kernel.  All apply the
  * same binary32 entries; kinds 1 and 2 differ in summation order only, and

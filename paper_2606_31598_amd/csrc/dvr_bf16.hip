@@ -12,7 +12,8 @@
 // 8 significant bits), each subtraction exact.  Products of pieces are exact
 // in binary32, so the six products whose piece levels sum to at most two
 // (hh, hm, mh, hl, lh, mm) reproduce t x up to the dropped mid-lo, lo-mid and
-// lo-lo terms, below 2^-25 |t x| and of either sign: the rounding level of a
+// lo-lo terms, at most 2^-23 |t x| (|mid| <= 2^-8 |v|, |lo| <= 2^-16 |v|;
+// root mean square about 2^-27) and of either sign: the rounding level of a
 // binary32 product.  They run as v_mfma_f32_32x32x16_bf16 with binary32
 // accumulation (the split-BF16 application of the paper's precision options,
 // with a third piece so that nothing coarser than binary32 rounding enters),
