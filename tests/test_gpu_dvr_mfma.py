@@ -56,6 +56,31 @@ def test_mfma_toeplitz_matches_oracle(pm, orc, D, kind):
         op.close()
 
 
+@pytest.mark.parametrize("D", [40000, 65536, 100003])
+def test_split_kernel_large_operators(pm, orc, D):
+    """Above the benchmark's size the chunks are as long as the LDS window
+    allows (70-72 offsets) and, for D = 100003, the last row group is
+    ragged; 256 sampled rows of each product against the binary64 row
+    oracle, both arithmetics."""
+    d = orc.DVR(D)
+    rows = workloads.sampled_rows(D, 256, seed=21)
+    X = workloads.gaussian_vectors(D, 1, seed=D % 1000).astype(np.complex64)
+    S = workloads.wavepacket(D).astype(np.complex64)
+    R = 0.5 * d.spectral_bounds()[1]
+    for prec in (pm.FP32, pm.FP32_COMPENSATED):
+        op = pm.Operator.dvr(D).plan(256, precision=prec).set_dvr_kernel(3)
+        err = rel_l2(to_host(op.apply(to_dev(X)))[:, rows], d.apply_rows(X, rows))
+        got_s = to_host(op.apply(to_dev(S)))[:, rows]
+        ref_s = d.apply_rows(S, rows)
+        err_s = rel_l2(got_s, ref_s)
+        sc = float(np.linalg.norm(got_s - ref_s) / (R * np.linalg.norm(S[:, rows])))
+        print(f"D={D} precision={prec} random {err:.2e} smooth {err_s:.2e} (scaled {sc:.1e})")
+        assert err < 1e-5
+        if prec == pm.FP32_COMPENSATED:
+            assert err_s < 1e-5 or sc < 1e-9
+        op.close()
+
+
 @pytest.mark.parametrize("kind", [2, 3])
 def test_mfma_and_valu_toeplitz_agree(pm, kind):
     """Same entries, different summation order (and, for kind 3, the
