@@ -20,28 +20,54 @@ struct Philox {
     static constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 };
 
+// a ^ b ^ c in one v_bitop3_b32 (truth table 0x96, the odd-parity function,
+// which is symmetric in its inputs); the compiler emits two v_xor_b32 for the
+// plain expression.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1,
                                              uint32_t& c2, uint32_t& c3,
                                              uint32_t k0, uint32_t k1)
 {
     uint64_t p0 = (uint64_t)Philox::M0 * c0;
     uint64_t p1 = (uint64_t)Philox::M1 * c2;
-    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+    uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
     c2 = n2;
 }
 
-// Words 0 and 1 of Philox4x32-10 at counter (i, j, 0, 0).
+// Words 0 and 1 of Philox4x32-10 at counter (i, j, 0, 0).  The first two
+// rounds are written out with the zero counter words folded away (round 1:
+// M1 * 0 = 0; round 2: its c1 is the low half of that zero product).
 __device__ __forceinline__ void philox_ij(uint32_t i, uint32_t j, uint32_t k0,
                                           uint32_t k1, uint32_t& x0,
                                           uint32_t& x1)
 {
-    uint32_t c0 = i, c1 = j, c2 = 0u, c3 = 0u;
+    // round 1: c = (i, j, 0, 0)
+    uint64_t p0 = (uint64_t)Philox::M0 * i;
+    uint32_t c0 = j ^ k0;
+    uint32_t c1 = 0u;
+    uint32_t c2 = (uint32_t)(p0 >> 32) ^ k1;
+    uint32_t c3 = (uint32_t)p0;
+    k0 += Philox::W0;
+    k1 += Philox::W1;
+    // round 2: c1 = 0
+    p0 = (uint64_t)Philox::M0 * c0;
+    uint64_t p1 = (uint64_t)Philox::M1 * c2;
+    c0 = (uint32_t)(p1 >> 32) ^ k0;
+    c2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    k0 += Philox::W0;
+    k1 += Philox::W1;
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
+    for (int r = 2; r < 10; ++r) {
         philox_round(c0, c1, c2, c3, k0, k1);
         k0 += Philox::W0;
         k1 += Philox::W1;
