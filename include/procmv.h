@@ -277,11 +277,15 @@ procmv_status procmv_get_entries(procmv_op_t H, int64_t r0, int64_t c0,
 /* Test hook for the generator's binary32 definition (paper Sec. III seeded
  * generation; the transform is fixed as IEEE operations): the kernels divide
  * and take square roots with short sequences (reciprocal or root estimate
- * plus one residual correction).  This runs, for all 2^23 uniforms the
- * generator can draw, the logarithm with the short division against the
- * compiler's IEEE division and the short square root of -2 ln u against the
- * IEEE square root, and returns the numbers of bitwise mismatches (host
- * int32s; both 0 means the entries equal the IEEE definition).  Allocates
+ * plus one residual correction) and evaluate the logarithm, sine and cosine
+ * in a rearranged but bitwise equal form (uniform scaled by 2^32, factor -2
+ * folded into the series constants, quadrant signs by XOR).  This runs, for
+ * all 2^23 uniforms the generator can draw, the logarithm with the short
+ * division against the compiler's IEEE division, the rearranged -2 ln u,
+ * sine and cosine against the plain ones (counted with the logarithm), and
+ * the short square root of -2 ln u against the IEEE square root, and returns
+ * the numbers of bitwise mismatches (host int32s; both 0 means the entries
+ * equal the IEEE definition).  Allocates
  * and frees 8 bytes of device memory; SYNCHRONISES the stream. */
 procmv_status procmv_selftest_generator(int32_t* ln_mismatches,
                                         int32_t* sqrt_mismatches, void* stream);

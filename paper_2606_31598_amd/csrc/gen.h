@@ -76,6 +76,50 @@ __device__ __forceinline__ void philox_ij(uint32_t i, uint32_t j, uint32_t k0,
     x1 = c1;
 }
 
+// The same words when i is the same in every lane of the wave (the matrix-core
+// tile kernel generates one row per wave and step).  Rounds 1 and 2 then
+// depend on the lane only through j, and the three-word XORs of rounds 2 and
+// 3 pair their two row-only words first, which the scalar unit does; the
+// rest is philox_ij's sequence.  The words are the same bits either way (XOR
+// is associative).
+__device__ __forceinline__ void philox_row(uint32_t i, uint32_t j, uint32_t k0, uint32_t k1,
+                                           uint32_t& x0, uint32_t& x1)
+{
+    // round 1: c = (i, j, 0, 0)
+    uint64_t p0 = (uint64_t)Philox::M0 * i;
+    uint32_t c0 = j ^ k0;
+    uint32_t c2 = (uint32_t)(p0 >> 32) ^ k1;
+    uint32_t c3 = (uint32_t)p0;
+    k0 += Philox::W0;
+    k1 += Philox::W1;
+    // round 2: c1 = 0; c2 and c3 are row-only, c0 lane-only
+    p0 = (uint64_t)Philox::M0 * c0;
+    uint64_t p1 = (uint64_t)Philox::M1 * c2;
+    c0 = (uint32_t)(p1 >> 32) ^ k0;
+    c2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);
+    uint32_t c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    k0 += Philox::W0;
+    k1 += Philox::W1;
+    // round 3: c0 and c1 are row-only
+    p0 = (uint64_t)Philox::M0 * c0;
+    p1 = (uint64_t)Philox::M1 * c2;
+    c0 = (uint32_t)(p1 >> 32) ^ (c1 ^ k0);
+    c2 = c3 ^ ((uint32_t)(p0 >> 32) ^ k1);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    k0 += Philox::W0;
+    k1 += Philox::W1;
+#pragma unroll
+    for (int r = 3; r < 10; ++r) {
+        philox_round(c0, c1, c2, c3, k0, k1);
+        k0 += Philox::W0;
+        k1 += Philox::W1;
+    }
+    x0 = c0;
+    x1 = c1;
+}
+
 // Uniform (2 (x >> 9) + 1) 2^-24 in (0, 1), exact in binary32.
 __device__ __forceinline__ float u01(uint32_t x)
 {
@@ -162,14 +206,84 @@ __device__ __forceinline__ void sincos_turn(float u, float& sv, float& cv)
     cv = ((q + 1) & 2) ? -c0 : c0;
 }
 
-// Box-Muller: z0 = r cos(2 pi u1), z1 = r sin(2 pi u1), r = sqrt(-2 ln u0).
+// The kernels' form of the transform below: the same binary32 results,
+// bit for bit, in fewer instructions (procmv_selftest_generator compares
+// both forms over every uniform).
+//  * The uniform is kept as Z = u 2^32 = (x with its low nine bits replaced
+//    by 1 0000 0000): at most 24 significant bits, so the conversion is
+//    exact, and Z has u's significand.
+//  * -2 ln u takes Z's exponent minus 159 (= 127 + 32) and the series and
+//    ln 2 constants times -2; scaling by a power of two commutes with every
+//    rounding here (no result is near the binary32 range limits).
+//  * sin and cos reach their quadrant signs by XOR of the sign bit.
+__device__ __forceinline__ float unit_2p32(uint32_t x)
+{
+    // 0x100 held in a register lets the mask and the insert be one
+    // v_and_or_b32 (a three-operand instruction takes no literal)
+    uint32_t c = 0x100u;
+    asm("" : "+v"(c));
+    return (float)((x & 0xFFFFFE00u) | c);
+}
+
+__device__ __forceinline__ float neg2_ln_2p32(float z)
+{
+    uint32_t b = __float_as_uint(z);
+    int e = (int)(b >> 23) - 159;
+    float m = __uint_as_float((b & 0x007FFFFFu) | 0x3F800000u);
+    if (m > 1.41421356237309504880f) {
+        m = m * 0.5f;
+        e = e + 1;
+    }
+    float f = m - 1.0f;
+    float s = div_gen(f, 2.0f + f);
+    float s2 = s * s;
+    float p = __builtin_fmaf(s2, -2.0f * (float)(2.0 / 9.0), -2.0f * (float)(2.0 / 7.0));
+    p = __builtin_fmaf(s2, p, -2.0f * (float)(2.0 / 5.0));
+    p = __builtin_fmaf(s2, p, -2.0f * (float)(2.0 / 3.0));
+    float lm = __builtin_fmaf(s * s2, p, -4.0f * s);
+    float ef = (float)e;
+    const float ln2_hi = 0.693147180559945309417f;
+    const float ln2_lo = (float)(0.693147180559945309417232121458 -
+                                 (double)0.693147180559945309417f);
+    return __builtin_fmaf(ef, -2.0f * ln2_hi, __builtin_fmaf(ef, -2.0f * ln2_lo, lm));
+}
+
+__device__ __forceinline__ void sincos_2p32(float z, float& sv, float& cv)
+{
+    const float u = z * 0x1p-32f;
+    const float n = __builtin_rintf(z * 0x1p-30f);     // 4u
+    const float r = __builtin_fmaf(n, -0.25f, u);
+    float r2 = r * r;
+    float ps = __builtin_fmaf(r2, 42.0586939448976531450f, -76.7058597530613858416f);
+    ps = __builtin_fmaf(r2, ps, 81.6052492760750542034f);
+    ps = __builtin_fmaf(r2, ps, -41.3417022403997602340f);
+    ps = __builtin_fmaf(r2, ps, 6.28318530717958647692f);
+    const float sr = r * ps;
+    float pc = __builtin_fmaf(r2, -26.4262567833743974529f, 60.2446413718766603627f);
+    pc = __builtin_fmaf(r2, pc, -85.4568172066937277360f);
+    pc = __builtin_fmaf(r2, pc, 64.9393940226682914910f);
+    pc = __builtin_fmaf(r2, pc, -19.7392088021787172377f);
+    const float cr = __builtin_fmaf(r2, pc, 1.0f);
+    const int q = (int)n;                              // 0 .. 4; 4 is quadrant 0
+    const float s0 = (q & 1) ? cr : sr;
+    const float c0 = (q & 1) ? sr : cr;
+    // s ^ (t & sign) as one v_bitop3_b32: the function S1 ^ (S0 & S2) (table
+    // 0x6c) is symmetric in S0 and S2
+    const uint32_t sign = 0x80000000u;
+    sv = __uint_as_float(__builtin_amdgcn_bitop3_b32((uint32_t)q << 30, __float_as_uint(s0),
+                                                     sign, 0x6c));
+    cv = __uint_as_float(__builtin_amdgcn_bitop3_b32((uint32_t)(q + 1) << 30,
+                                                     __float_as_uint(c0), sign, 0x6c));
+}
+
+// Box-Muller: z0 = r cos(2 pi u1), z1 = r sin(2 pi u1), r = sqrt(-2 ln u0),
+// u = u01(x) (the definitions above), in the kernels' form.
 __device__ __forceinline__ void box_muller(uint32_t x0, uint32_t x1, float& z0,
                                            float& z1)
 {
-    float l = ln_unit(u01(x0));
-    float r = sqrt_gen(-2.0f * l);
+    float r = sqrt_gen(neg2_ln_2p32(unit_2p32(x0)));
     float sv, cv;
-    sincos_turn(u01(x1), sv, cv);
+    sincos_2p32(unit_2p32(x1), sv, cv);
     z0 = r * cv;
     z1 = r * sv;
 }
