@@ -78,8 +78,8 @@ __device__ __forceinline__ void philox_ij(uint32_t i, uint32_t j, uint32_t k0,
 
 // The same words when i is the same in every lane of the wave (the matrix-core
 // tile kernel generates one row per wave and step).  Rounds 1 and 2 then
-// depend on the lane only through j, and the three-word XORs of rounds 2 and
-// 3 pair their two row-only words first, which the scalar unit does; the
+// depend on the lane only through j, and the three-word XORs of rounds 2 to
+// 4 pair their two row-only words first, which the scalar unit does; the
 // rest is philox_ij's sequence.  The words are the same bits either way (XOR
 // is associative).
 __device__ __forceinline__ void philox_row(uint32_t i, uint32_t j, uint32_t k0, uint32_t k1,
@@ -110,8 +110,17 @@ __device__ __forceinline__ void philox_row(uint32_t i, uint32_t j, uint32_t k0, 
     c3 = (uint32_t)p0;
     k0 += Philox::W0;
     k1 += Philox::W1;
+    // round 4: c3 is row-only
+    p0 = (uint64_t)Philox::M0 * c0;
+    p1 = (uint64_t)Philox::M1 * c2;
+    c0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+    c2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    k0 += Philox::W0;
+    k1 += Philox::W1;
 #pragma unroll
-    for (int r = 3; r < 10; ++r) {
+    for (int r = 4; r < 10; ++r) {
         philox_round(c0, c1, c2, c3, k0, k1);
         k0 += Philox::W0;
         k1 += Philox::W1;
