@@ -42,7 +42,9 @@ def _unpack(buf, sizes, nvec):
     return out
 
 
-@pytest.mark.parametrize("nvec", [1, 4])
+# nvec = 8 takes the matrix cores: the batch runs the four-wave kernel form and
+# single products the eight-wave form, which must agree bit for bit
+@pytest.mark.parametrize("nvec", [1, 4, 8])
 def test_batched_apply_equals_per_instance(pm, orc, nvec):
     import torch
     sizes = [700, 64, 1500, 257, 1024, 3, 999, 11520]
