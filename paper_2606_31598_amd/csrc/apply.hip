@@ -139,7 +139,9 @@ __device__ __forceinline__ void super_tile(const TileArgs& a, int sr, int sc,
     const int SR = 64 * sct / TR;       // tile rows (the launcher keeps TR <= edge)
 
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    // wave index visibly uniform: a wave's row indices are scalars, and the
+    // Philox products that depend on the row only run on the scalar unit
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool diag_st = (sr == sc);
     const int row0 = sr * 64 * sct, col0 = sc * 64 * sct;
     const int D = a.D;
@@ -229,10 +231,10 @@ __device__ __forceinline__ void super_tile(const TileArgs& a, int sr, int sc,
                     const bool ok = jin && (i < D) && (i <= j);
                     const bool upper = ok && (i < j);
                     if (GEN == 0) {
-                        const uint32_t ic = ok ? (uint32_t)i : 0u;
-                        const uint32_t jc = ok ? (uint32_t)j : 1u;
+                        // every lane draws at its own (i, j); entries outside the
+                        // operator or below the diagonal are masked to zero below
                         uint32_t x0, x1;
-                        philox_ij(ic, jc, a.src.gue.k0, a.src.gue.k1, x0, x1);
+                        philox_row((uint32_t)i, (uint32_t)j, a.src.gue.k0, a.src.gue.k1, x0, x1);
                         float z0, z1;
                         box_muller(x0, x1, z0, z1);
                         float2 h = (i == j) ? make_float2(a.src.gue.s_diag * z0, 0.f)
