@@ -349,6 +349,7 @@ struct TileOut {
     int32_t nv_stride = 0;
     const float* vdiag = nullptr;
     float2* P = nullptr;      // partial slots written by the tile kernels
+    int32_t xcd_groups = 0;   // split-bf16 row groups pinned to XCDs (see ReduceArgs)
 };
 
 // Caller-provided partial buffer (the allocation-free product); null = the
@@ -433,8 +434,14 @@ procmv_status run_tiles(procmv_op* op, const float2* X, int64_t ldx, int nv,
         a.ldx = ldx;
         a.P = out.P;
         a.ldp = (int64_t)ldp;
-        if (tbf16)
+        if (tbf16) {
             HIP_TRY(launch_dvr_toeplitz_bf16(a, s, timed ? e0 : nullptr, e1));
+            // 2048-row groups, a multiple of 8 of them: every chunk of group g
+            // is workgroup g + groups c, on XCD g mod 8
+            const int64_t groups = op->D / 2048;
+            if (op->D % 2048 == 0 && groups % 8 == 0)
+                out.xcd_groups = (int32_t)groups;
+        }
         else if (tmfma)
             HIP_TRY(launch_dvr_toeplitz_mfma(a, s, timed ? e0 : nullptr, e1));
         else
@@ -530,6 +537,7 @@ procmv_status run_product(procmv_op* op, const float2* X, int64_t ldx, int nv, R
     r.P = base.P;
     r.ldp = base.ldp;
     r.vdiag = base.vdiag;
+    r.xcd_groups = to.xcd_groups;
     r.X = X;
     r.ldx = ldx;
     return run_reduce(op, r, mode, s, scr.p != nullptr);
