@@ -127,11 +127,12 @@ struct ReduceArgs {
     float2* Xlo_zero;         // kChebFirst: lo buffer of q0, set to zero
     int64_t ldylo;
     float gamma_hi, gamma_lo; // alpha c as a hi + lo pair
-    // > 0: the partial slots come from the split-bf16 Toeplitz kernel, whose
-    // row group g (xcd_groups of them, a multiple of 8; 32 blocks of 64 rows
-    // each, D = 2048 xcd_groups) ran every chunk on XCD g mod 8: the
-    // reduction's workgroup b (XCD b mod 8) takes a 64-row block of a group
-    // on its own XCD, so that it reads the slots through that XCD's L2
+    // > 0 (one vector): the partial slots come from the split-bf16 Toeplitz
+    // kernel, whose row group g (xcd_groups of them, a multiple of 8; 32
+    // blocks of 64 rows each, D = 2048 xcd_groups) ran every chunk on XCD
+    // g mod 8: the reduction's workgroup b (XCD b mod 8) takes a 64-row
+    // block of a group on its own XCD, so that it reads the slots through
+    // that XCD's L2
     int32_t xcd_groups;
 };
 
