@@ -530,14 +530,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
     // sums are combined in a fixed order.
     __shared__ float2 part[4][64];
     const int g = threadIdx.x >> 6;
-    int64_t rb = blockIdx.x;
-    if (a.xcd_groups > 0) {
-        // one vector from the split-bf16 kernel: take a 64-row block of a
-        // row group that ran on this workgroup's XCD (round robin by index)
-        const int x = (int)(rb & 7), w = (int)(rb >> 3);
-        rb = (int64_t)(x + 8 * (w >> 5)) * 32 + (w & 31);
-    }
-    const int64_t t = rb * 64 + (threadIdx.x & 63);
+    const int64_t t = (int64_t)reduce_row_block(a, blockIdx.x) * 64 + (threadIdx.x & 63);
     const int64_t total = (int64_t)a.nv * a.D;
     const bool live = t < total;
     const int v = live ? (int)(t / a.D) : 0;

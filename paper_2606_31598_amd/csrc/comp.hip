@@ -67,13 +67,7 @@ __global__ __launch_bounds__(256) void reduce_comp_kernel(ReduceArgs a)
     const int W = a.W;                           // 1 <= W <= kNearBand
     const int D = a.D;
     const int v = blockIdx.y;
-    int rb = blockIdx.x;
-    if (a.xcd_groups > 0) {
-        // workgroups go to the XCDs round robin by index
-        const int x = rb & 7, t = rb >> 3;
-        rb = (x + 8 * (t >> 5)) * 32 + (t & 31);
-    }
-    const int r0 = rb * 64;
+    const int r0 = reduce_row_block(a, blockIdx.x) * 64;
     const int g = threadIdx.x >> 6;
     const int l = threadIdx.x & 63;
     const int i = r0 + l;

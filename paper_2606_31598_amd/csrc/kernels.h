@@ -140,6 +140,17 @@ struct ReduceArgs {
 // summed in difference form by the reduction, W = min(kNearBand, D).
 constexpr int kNearBand = 32;
 
+// 64-row block reduced by workgroup b: b itself, or with a.xcd_groups > 0 a
+// block of a split-kernel row group that ran on b's XCD (workgroups go to the
+// eight XCDs round robin by index; group g's 32 blocks sit on XCD g mod 8).
+// A permutation of the 32 xcd_groups blocks.
+__device__ __forceinline__ int reduce_row_block(const ReduceArgs& a, int b)
+{
+    if (a.xcd_groups <= 0) return b;
+    const int x = b & 7, w = b >> 3;
+    return (x + 8 * (w >> 5)) * 32 + (w & 31);
+}
+
 // Epilogue of the fixed-order reduction for output element (v, i) whose
 // summed partials are (sx, sy): add the site diagonal, scale, add the
 // constant diagonal, then store (product) or advance the Chebyshev
